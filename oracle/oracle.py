@@ -87,6 +87,8 @@ def lib():
         L.or_destroy.argtypes = [C.c_void_p]
         L.or_add_species.argtypes = [C.c_void_p, C.POINTER(Species), C.c_size_t, _D, _D, _D]
         L.or_init_species.argtypes = [C.c_void_p, C.POINTER(Species), C.POINTER(Init), C.POINTER(C.c_int)]
+        L.or_species_weight.restype = C.c_double
+        L.or_species_weight.argtypes = [C.c_void_p, C.c_int]
         L.or_count.restype = C.c_size_t
         L.or_count.argtypes = [C.c_void_p, C.c_int]
         L.or_get_particles.argtypes = [C.c_void_p, C.c_int, _D, _D, _D]
@@ -310,6 +312,17 @@ class Sim:
 
     def count(self, sid):
         return lib().or_count(self.h, sid)
+
+    def weight(self, sid):
+        return lib().or_species_weight(self.h, sid)
+
+    def state(self):
+        """(x, v, xi or None, weight) per species, for injecting the same state elsewhere."""
+        out = []
+        for sid, sp in enumerate(self.species):
+            x, v, xi = self.particles(sid)
+            out.append((x, v, xi if sp["kind"] == "bound" else None, self.weight(sid)))
+        return out
 
     def particles(self, sid):
         n = self.count(sid)

@@ -392,10 +392,15 @@ int or_reflect(const or_species* s, int dims, double X[3], double v[3])
 /* ------------------------------------------------------------------------- */
 #define OR_MAX_SPECIES 8
 
+/* Positions are carried as an integer cell index plus an offset in [0,1) along
+ * each active axis (cell units), so that a step's move of 1e-6 cell or less is
+ * not lost to the rounding of an absolute coordinate.  Bound particles keep
+ * their anchor in C, O and their displacement in xi. */
 typedef struct {
     or_species sp;
     size_t n;
-    double* X;  /* [n][3] position in cell units (bound: anchor)           */
+    long* C;    /* [n][3] cell index (bound: anchor cell)                  */
+    double* O;  /* [n][3] in-cell offset in [0,1) (bound: anchor offset)   */
     double* v;  /* [n][3] velocity v_{n-1/2} [m/s]                         */
     double* xi; /* [n][3] bound displacement from the anchor [m]           */
 } sp_state;
@@ -499,7 +504,7 @@ void or_destroy(or_sim* s)
     if (!s) return;
     for (int c = 0; c < 3; ++c) { free(s->E[c]); free(s->B[c]); free(s->J[c]); }
     free(s->rho_ion);
-    for (int i = 0; i < s->nsp; ++i) { free(s->sp[i].X); free(s->sp[i].v); free(s->sp[i].xi); }
+    for (int i = 0; i < s->nsp; ++i) { free(s->sp[i].C); free(s->sp[i].O); free(s->sp[i].v); free(s->sp[i].xi); }
     free(s->series);
     free(s);
 }
@@ -525,17 +530,27 @@ static double* dup3(const double* src, size_t n, double scale0, double scale1, d
     return d;
 }
 
-static void wrap_position(const or_sim* s, double X[3])
+/* Renormalise a position to offset in [0,1) and wrap the cell on periodic axes. */
+static void normalize(const or_sim* s, long C[3], double O[3])
 {
     for (int a = 0; a < s->g.dims; ++a) {
-        if (!s->g.periodic[a]) continue;
-        double n = (double)s->g.n[a];
-        if (X[a] >= n) X[a] -= n;
-        else if (X[a] < 0.0) {
-            X[a] += n;
-            if (X[a] >= n) X[a] = 0.0;
+        double f = floor(O[a]);
+        C[a] += (long)f;
+        O[a] -= f;
+        if (O[a] >= 1.0) { O[a] = 0.0; C[a] += 1; }
+        if (s->g.periodic[a]) {
+            long n = s->g.n[a];
+            C[a] = ((C[a] % n) + n) % n;
         }
     }
+}
+
+/* Cell and offset of an absolute position X (cell units). */
+static void set_position(const or_sim* s, const double X[3], long C[3], double O[3])
+{
+    for (int a = 0; a < 3; ++a) { C[a] = 0; O[a] = 0.0; }
+    for (int a = 0; a < s->g.dims; ++a) O[a] = X[a];
+    normalize(s, C, O);
 }
 
 int or_add_species(or_sim* s, const or_species* sp, size_t n,
@@ -545,14 +560,16 @@ int or_add_species(or_sim* s, const or_species* sp, size_t n,
     sp_state* st = &s->sp[s->nsp];
     st->sp = *sp;
     st->n = n;
-    double inv[3] = {1.0 / s->g.dx[0], 1.0 / s->g.dx[1], 1.0 / s->g.dx[2]};
-    st->X = dup3(x, n, inv[0], inv[1], inv[2]);
+    st->C = (long*)calloc(3 * (n ? n : 1), sizeof(long));
+    st->O = (double*)calloc(3 * (n ? n : 1), sizeof(double));
     st->v = dup3(v, n, 1.0, 1.0, 1.0);
     st->xi = dup3(sp->kind == OR_BOUND ? xi : NULL, n, 1.0, 1.0, 1.0);
-    if (!st->X || !st->v || !st->xi) return -2;
-    for (size_t i = 0; i < n; ++i)
-        for (int a = s->g.dims; a < 3; ++a) st->X[3 * i + a] = 0.0;
-    for (size_t i = 0; i < n; ++i) wrap_position(s, &st->X[3 * i]);
+    if (!st->C || !st->O || !st->v || !st->xi) return -2;
+    for (size_t i = 0; i < n; ++i) {
+        double X[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < s->g.dims; ++a) X[a] = x[3 * i + a] / s->g.dx[a];
+        set_position(s, X, &st->C[3 * i], &st->O[3 * i]);
+    }
     return s->nsp++;
 }
 
@@ -625,10 +642,11 @@ int or_init_species(or_sim* s, const or_species* spin, const or_init* ini, int* 
     sp_state* st = &s->sp[sid];
     st->sp = sp;
     st->n = n;
-    st->X = (double*)calloc(3 * (n ? n : 1), sizeof(double));
+    st->C = (long*)calloc(3 * (n ? n : 1), sizeof(long));
+    st->O = (double*)calloc(3 * (n ? n : 1), sizeof(double));
     st->v = (double*)calloc(3 * (n ? n : 1), sizeof(double));
     st->xi = (double*)calloc(3 * (n ? n : 1), sizeof(double));
-    if (!st->X || !st->v || !st->xi) { free(cells); return -2; }
+    if (!st->C || !st->O || !st->v || !st->xi) { free(cells); return -2; }
 
     double kT = KB * ini->temperature;
     fd_table* tab = NULL;
@@ -643,14 +661,16 @@ int or_init_species(or_sim* s, const or_species* spin, const or_init* ini, int* 
         int k = (int)(p % (size_t)ini->ppc);
         double u[6];
         draw6(ini->seed, sid, (uint64_t)p, u);
-        double* X = &st->X[3 * p];
+        long* Cp = &st->C[3 * p];
+        double* Op = &st->O[3 * p];
         double* v = &st->v[3 * p];
-        for (int a = 0; a < d; ++a) X[a] = (double)cells[3 * cr + a] + u[a];
+        for (int a = 0; a < d; ++a) { Cp[a] = cells[3 * cr + a]; Op[a] = u[a]; }
         if (ini->loading == OR_LOAD_QUIET) {
             double x0 = (double)cells[3 * cr] + ((double)k + 0.5) / (double)ini->ppc;
             double nx = (double)s->g.n[0];
             double kw = 2.0 * PI * (double)ini->pert_mode / nx; /* per cell */
-            X[0] = x0 + (ini->pert_amp / kw) * sin(kw * x0);
+            double X[3] = {x0 + (ini->pert_amp / kw) * sin(kw * x0), 0.0, 0.0};
+            set_position(s, X, Cp, Op);
         }
         if (sp.kind == OR_FREE) {
             if (ini->momentum == OR_MOM_FD) {
@@ -680,13 +700,17 @@ int or_init_species(or_sim* s, const or_species* spin, const or_init* ini, int* 
             st->xi[3 * p + 1] = r * st_ * sin(ph);
             st->xi[3 * p + 2] = r * ct;
         }
-        wrap_position(s, X);
     }
     free(tab);
     free(cells);
     s->nsp++;
     if (sid_out) *sid_out = sid;
     return 0;
+}
+
+double or_species_weight(const or_sim* s, int sid)
+{
+    return (sid >= 0 && sid < s->nsp) ? s->sp[sid].sp.weight : NAN;
 }
 
 size_t or_count(const or_sim* s, int sid)
@@ -700,7 +724,7 @@ int or_get_particles(const or_sim* s, int sid, double* x, double* v, double* xi)
     const sp_state* st = &s->sp[sid];
     for (size_t i = 0; i < st->n; ++i)
         for (int a = 0; a < 3; ++a) {
-            if (x) x[3 * i + a] = st->X[3 * i + a] * s->g.dx[a];
+            if (x) x[3 * i + a] = a < s->g.dims ? ((double)st->C[3 * i + a] + st->O[3 * i + a]) * s->g.dx[a] : 0.0;
             if (v) v[3 * i + a] = st->v[3 * i + a];
             if (xi) xi[3 * i + a] = st->xi[3 * i + a];
         }
@@ -721,11 +745,11 @@ static int32_t cell_key(const or_sim* s, const int c[3])
     return (int32_t)(tid * (long)T[0] * T[1] * T[2] + loc);
 }
 
-static int32_t particle_key(const or_sim* s, const double X[3])
+static int32_t particle_key(const or_sim* s, const long C[3])
 {
     int c[3] = {0, 0, 0};
     for (int a = 0; a < s->g.dims; ++a) {
-        c[a] = (int)floor(X[a]);
+        c[a] = (int)C[a];
         if (c[a] < 0) c[a] = 0;
         if (c[a] >= s->g.n[a]) c[a] = s->g.n[a] - 1;
     }
@@ -736,7 +760,7 @@ int or_keys(const or_sim* s, int sid, int32_t* keys)
 {
     if (sid < 0 || sid >= s->nsp) return -1;
     const sp_state* st = &s->sp[sid];
-    for (size_t i = 0; i < st->n; ++i) keys[i] = particle_key(s, &st->X[3 * i]);
+    for (size_t i = 0; i < st->n; ++i) keys[i] = particle_key(s, &st->C[3 * i]);
     return 0;
 }
 
@@ -751,20 +775,27 @@ static int sort_species(or_sim* s, sp_state* st)
     int32_t* key = (int32_t*)malloc(sizeof(int32_t) * n);
     size_t* perm = (size_t*)malloc(sizeof(size_t) * n);
     double* tmp = (double*)malloc(sizeof(double) * 3 * n);
-    if (!count || !key || !perm || !tmp) { free(count); free(key); free(perm); free(tmp); return -2; }
+    long* tmpc = (long*)malloc(sizeof(long) * 3 * n);
+    if (!count || !key || !perm || !tmp || !tmpc) {
+        free(count); free(key); free(perm); free(tmp); free(tmpc);
+        return -2;
+    }
     for (size_t i = 0; i < n; ++i) {
-        key[i] = particle_key(s, &st->X[3 * i]);
+        key[i] = particle_key(s, &st->C[3 * i]);
         count[key[i] + 1]++;
     }
     for (long k = 0; k < nkeys; ++k) count[k + 1] += count[k];
     for (size_t i = 0; i < n; ++i) perm[count[key[i]]++] = i;
-    double* arrs[3] = {st->X, st->v, st->xi};
+    double* arrs[3] = {st->O, st->v, st->xi};
     for (int w = 0; w < 3; ++w) {
         for (size_t i = 0; i < n; ++i)
             for (int a = 0; a < 3; ++a) tmp[3 * i + a] = arrs[w][3 * perm[i] + a];
         memcpy(arrs[w], tmp, sizeof(double) * 3 * n);
     }
-    free(count); free(key); free(perm); free(tmp);
+    for (size_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) tmpc[3 * i + a] = st->C[3 * perm[i] + a];
+    memcpy(st->C, tmpc, sizeof(long) * 3 * n);
+    free(count); free(key); free(perm); free(tmp); free(tmpc);
     return 0;
 }
 
@@ -782,14 +813,14 @@ int or_sort(or_sim* s)
 /* Reading: first-order (cloud-in-cell) weights on each component's own      */
 /* staggered location.                                                       */
 /* ------------------------------------------------------------------------- */
-static double gather(const or_sim* s, const double* F, const int half[3], const double X[3])
+static double gather(const or_sim* s, const double* F, const int half[3], const long C[3], const double O[3])
 {
     long base[3] = {0, 0, 0};
     double w1[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < s->g.dims; ++a) {
-        double u = X[a] - (half[a] ? 0.5 : 0.0);
+        double u = O[a] - (half[a] ? 0.5 : 0.0);
         double f = floor(u);
-        base[a] = (long)f;
+        base[a] = C[a] + (long)f;
         w1[a] = u - f;
     }
     double sum = 0.0;
@@ -806,21 +837,23 @@ static double gather(const or_sim* s, const double* F, const int half[3], const 
     return sum;
 }
 
-static void gather_EB(const or_sim* s, const double X[3], double E[3], double B[3])
+static void gather_EB(const or_sim* s, const long C[3], const double O[3], double E[3], double B[3])
 {
     int h[3];
     for (int c = 0; c < 3; ++c) {
-        stag_E(c, h); E[c] = gather(s, s->E[c], h, X);
-        stag_B(c, h); B[c] = gather(s, s->B[c], h, X);
+        stag_E(c, h); E[c] = gather(s, s->E[c], h, C, O);
+        stag_B(c, h); B[c] = gather(s, s->B[c], h, C, O);
     }
 }
 
 /* Fields at a point x (metres), for tests. */
 int or_gather_at(const or_sim* s, const double x[3], double E[3], double B[3])
 {
-    double X[3] = {0.0, 0.0, 0.0};
+    double X[3] = {0.0, 0.0, 0.0}, O[3];
+    long C[3];
     for (int a = 0; a < s->g.dims; ++a) X[a] = x[a] / s->g.dx[a];
-    gather_EB(s, X, E, B);
+    set_position(s, X, C, O);
+    gather_EB(s, C, O, E, B);
     return 0;
 }
 
@@ -828,29 +861,32 @@ int or_gather_at(const or_sim* s, const double x[3], double E[3], double B[3])
 /* Charge-conserving current deposition.  The paper deposits J_f from the    */
 /* macroparticles (eq:consteps) without naming the scheme.  Reading:          */
 /* Esirkepov (Comput. Phys. Commun. 135, 144 (2001)) with first-order shapes  */
-/* S(x) = max(0, 1 - |x|) along the straight segment X0 -> X1 (cell units).   */
+/* S(x) = max(0, 1 - |x|) along the straight segment from x0 to x1, both      */
+/* given relative to the start cell c0 (cell units).  Reading: the move is    */
+/* the push displacement dt v_{n+1/2} (eq:discrvel, and xi_{n+1} - xi_n for a */
+/* bound particle), added to the start offset, so it is not recomputed as a   */
+/* difference of rounded absolute positions.                                  */
 /* ------------------------------------------------------------------------- */
 static double shape1(double x) { double a = fabs(x); return a < 1.0 ? 1.0 - a : 0.0; }
 
-static void deposit(or_sim* s, double qw, const double X0[3], const double X1[3], const double v[3])
+static void deposit(or_sim* s, double qw, const long c0[3], const double x0[3], const double x1[3],
+                    const double v[3])
 {
     int d = s->g.dims;
     const double* dx = s->g.dx;
     const double dt = s->g.dt;
-    long c0[3] = {0, 0, 0};
     double S0[3][4], S1[3][4], DS[3][4];
     for (int a = 0; a < 3; ++a)
         for (int m = 0; m < 4; ++m) { S0[a][m] = S1[a][m] = DS[a][m] = 0.0; }
     for (int a = 0; a < d; ++a) {
-        c0[a] = (long)floor(X0[a]);
-        if (fabs(X1[a] - X0[a]) >= 1.0) {
+        if (fabs(x1[a] - x0[a]) >= 1.0) {
             fprintf(stderr, "pic_oracle: displacement of a cell or more in one step\n");
             abort();
         }
         for (int m = 0; m < 4; ++m) {
-            double node = (double)(c0[a] + m - 1);
-            S0[a][m] = shape1(X0[a] - node);
-            S1[a][m] = shape1(X1[a] - node);
+            double node = (double)(m - 1);
+            S0[a][m] = shape1(x0[a] - node);
+            S1[a][m] = shape1(x1[a] - node);
             DS[a][m] = S1[a][m] - S0[a][m];
         }
     }
@@ -924,12 +960,14 @@ static void deposit_rho(const or_sim* s, double* rho)
         const sp_state* st = &s->sp[i];
         double qw = st->sp.q * st->sp.weight;
         for (size_t p = 0; p < st->n; ++p) {
-            double X[3];
-            for (int a = 0; a < 3; ++a)
-                X[a] = st->X[3 * p + a] + (st->sp.kind == OR_BOUND && a < d ? st->xi[3 * p + a] / s->g.dx[a] : 0.0);
             long b[3] = {0, 0, 0};
             double w1[3] = {0, 0, 0};
-            for (int a = 0; a < d; ++a) { b[a] = (long)floor(X[a]); w1[a] = X[a] - (double)b[a]; }
+            for (int a = 0; a < d; ++a) {
+                double r = st->O[3 * p + a] + (st->sp.kind == OR_BOUND ? st->xi[3 * p + a] / s->g.dx[a] : 0.0);
+                double f = floor(r);
+                b[a] = st->C[3 * p + a] + (long)f;
+                w1[a] = r - f;
+            }
             int na[3] = {1, 1, 1};
             for (int a = 0; a < d; ++a) na[a] = 2;
             for (int dk = 0; dk < na[2]; ++dk)
@@ -1103,31 +1141,40 @@ static void particle_step(or_sim* s, double I[3])
         const or_species* sp = &st->sp;
         double qm = sp->q / sp->m, qw = sp->q * sp->weight;
         for (size_t p = 0; p < st->n; ++p) {
-            double* Xs = &st->X[3 * p];
+            long* Cp = &st->C[3 * p];
+            double* Op = &st->O[3 * p];
             double* v = &st->v[3 * p];
             double* xi = &st->xi[3 * p];
-            double X0[3], X1[3], E[3], B[3];
-            for (int a = 0; a < 3; ++a)
-                X0[a] = Xs[a] + (sp->kind == OR_BOUND && a < d ? xi[a] / s->g.dx[a] : 0.0);
-            gather_EB(s, X0, E, B);
+            long c0[3] = {0, 0, 0};
+            double x0[3] = {0.0, 0.0, 0.0}, x1[3] = {0.0, 0.0, 0.0}, E[3], B[3];
+            /* start cell and offset of x_n (bound: anchor plus displacement) */
+            for (int a = 0; a < d; ++a) {
+                double r = Op[a] + (sp->kind == OR_BOUND ? xi[a] / s->g.dx[a] : 0.0);
+                double f = floor(r);
+                c0[a] = Cp[a] + (long)f;
+                x0[a] = r - f;
+                if (x0[a] >= 1.0) { x0[a] = 0.0; c0[a] += 1; }
+            }
+            gather_EB(s, c0, x0, E, B);
             if (sp->kind == OR_FREE) or_push_free(qm, dt, E, B, v);
             else if (sp->kind == OR_BOUND)
                 or_push_bound(qm, dt, sp->omega0_sq, sp->gamma, sp->b_weight, E, B, xi, v);
             else or_push_dirac(qm, dt, sp->v_f, sp->sheet_normal, E, B, v);
+            /* x_{n+1} = x_n + dt v_{n+1/2} (eq:discrvel; xi_{n+1} = xi_n + dt v for bound particles) */
+            for (int a = 0; a < d; ++a) x1[a] = x0[a] + dt * v[a] / s->g.dx[a];
             if (sp->kind == OR_BOUND) {
-                /* xi_{n+1} = xi_n + dt v_{n+1/2} */
                 for (int a = 0; a < 3; ++a) xi[a] = xi[a] + dt * v[a];
-                for (int a = 0; a < 3; ++a) X1[a] = Xs[a] + (a < d ? xi[a] / s->g.dx[a] : 0.0);
-            } else {
-                /* x_{n+1} = x_n + dt v_{n+1/2} (eq:discrvel), in cell units */
-                for (int a = 0; a < 3; ++a) X1[a] = X0[a] + (a < d ? dt * v[a] / s->g.dx[a] : 0.0);
-                if (sp->reflect) or_reflect(sp, d, X1, v);
+            } else if (sp->reflect) {
+                double X[3] = {0.0, 0.0, 0.0};
+                for (int a = 0; a < d; ++a) X[a] = (double)c0[a] + x1[a];
+                if (or_reflect(sp, d, X, v))
+                    for (int a = 0; a < d; ++a) x1[a] = X[a] - (double)c0[a];
             }
-            deposit(s, qw, X0, X1, v);
+            deposit(s, qw, c0, x0, x1, v);
             for (int a = 0; a < 3; ++a) I[a] += qw * v[a];
             if (sp->kind != OR_BOUND) {
-                for (int a = 0; a < 3; ++a) Xs[a] = X1[a];
-                wrap_position(s, Xs);
+                for (int a = 0; a < d; ++a) { Cp[a] = c0[a]; Op[a] = x1[a]; }
+                normalize(s, Cp, Op);
             }
         }
     }

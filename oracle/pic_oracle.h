@@ -112,6 +112,7 @@ int  or_add_species(or_sim* s, const or_species* sp, size_t n,
                     const double* x, const double* v, const double* xi);
 int  or_init_species(or_sim* s, const or_species* sp, const or_init* ini, int* sid);
 size_t or_count(const or_sim* s, int sid);
+double or_species_weight(const or_sim* s, int sid);
 int  or_get_particles(const or_sim* s, int sid, double* x, double* v, double* xi);
 int  or_keys(const or_sim* s, int sid, int32_t* keys);
 size_t or_field_len(const or_sim* s);
