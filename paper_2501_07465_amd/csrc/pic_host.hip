@@ -1,0 +1,1267 @@
+// pic_host.hip -- host side of libpic: the C ABI of include/pic.h.
+//
+// Validates descriptors, plans the device arena (the library never allocates device memory),
+// builds the loader tables, enqueues the loaders, the cell sort, the particle and field kernels
+// and the FP64 diagnostics on the caller's stream, and optionally replays one sort period of
+// steps as a HIP graph.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pic.h"
+#include "pic_internal.h"
+#include "pic_sort.h"
+
+using namespace pic;
+
+namespace {
+
+constexpr int kFdTab = 65536;       // FD inverse-CDF intervals
+constexpr int kDiagBlocks = 1024;   // blocks of the diagnostic reductions
+constexpr size_t kAlign = 256;
+
+struct SpeciesHost {
+    pic_species_desc d;
+    uint64_t seed = 0;
+    long long n = 0;
+    double density = 0.0, weight = 0.0, mass = 0.0;
+    std::vector<int> cells;       // packed region cells (loader)
+    std::vector<double> cdf;      // FD table (loader, T > 0)
+    double e_max = 0.0;
+    // device buffers: [0] and [1] copies; parity says which is current
+    int* cell[2] = {nullptr, nullptr};
+    void* off[2][3] = {};
+    void* v[2][3] = {};
+    void* xi[2][3] = {};
+    int parity = 0;
+    int* dcells = nullptr;
+    double* dcdf = nullptr;
+    bool sorted_once = false;
+};
+
+}  // namespace
+
+struct pic_sim {
+    pic_grid_desc g{};
+    std::vector<SpeciesHost> sp;
+    SimDev h{};              // host mirror of the device table
+    SimDev* d = nullptr;     // device table (in the arena)
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    hipStream_t st = nullptr;
+    bool bound = false;
+    long long step = 0;
+    bool need_sort = true;
+    std::string err;
+    int es = 4;              // element size of reals
+    int passes = 1;
+    int pgrid = 1;
+    int field_lds = 0;
+    int max_slots = 0;
+    bool graphs = false;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int> graph_species;  // species sorted inside the captured period
+    double* part = nullptr;  // diagnostic partials [kDiagBlocks * 4]
+    double* outv = nullptr;  // diagnostic results [16]
+    double* cont = nullptr;  // last continuity residual [2]
+    int batch_refs = 0;      // member of a batch
+    SimDev* d_batch = nullptr;  // the member's entry in the batch table
+};
+
+// The device table the kernels of this simulation must read: its own, or its batch entry.
+static SimDev* dtab(pic_sim* s) { return s->batch_refs ? s->d_batch : s->d; }
+
+struct pic_batch {
+    int max_sims = 0, dims = 0, precision = 0;
+    SimDev* table = nullptr;  // device [max_sims]
+    hipStream_t st = nullptr;
+    std::vector<pic_sim*> members;
+    std::string err;
+    hipGraphExec_t gexec = nullptr;
+    int graph_k = 0;
+    bool dirty = true;
+};
+
+static int fail(pic_sim* s, int code, const char* fmt, ...)
+{
+    if (s) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        s->err = buf;
+    }
+    return code;
+}
+
+static thread_local std::string g_create_err;
+
+#define HIPCHK(sim, expr)                                                                           \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess) return fail(sim, PIC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+static bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+static int ilog2(int x) { int r = 0; while ((1 << r) < x) ++r; return r; }
+
+// ---------------------------------------------------------------------------------------------
+// Closed forms the loader needs (Sec. 2, Sec. 5, eq:dtlimit)
+// ---------------------------------------------------------------------------------------------
+// Density of a free-electron gas with Fermi energy E_F: n = (2 m E_F / hbar^2)^{3/2} / (3 pi^2)
+// (the Fermi-energy relation of Sec. 2 with exponent 2/3 on (3 pi^2 n)).
+static double density_from_fermi(double ef, double m)
+{
+    return std::pow(2.0 * m * ef / (kHbar * kHbar), 1.5) / (3.0 * kPi * kPi);
+}
+
+// Dirac sheet density with fourfold degeneracy, n_2D = (E_F / (hbar v_F))^2 / pi.
+static double dirac_density2d(double ef, double vf)
+{
+    const double kf = ef / (kHbar * vf);
+    return kf * kf / kPi;
+}
+
+// m_d = p_F / (2 v_F), p_F = E_F / v_F (Sec. 5)
+static double dirac_mass(double ef, double vf) { return (ef / vf) / (2.0 * vf); }
+
+// ---------------------------------------------------------------------------------------------
+// Grid validation and derived geometry
+// ---------------------------------------------------------------------------------------------
+static int setup_grid(pic_sim* s)
+{
+    pic_grid_desc& g = s->g;
+    SimDev& h = s->h;
+    if (g.dims < 1 || g.dims > 3) return fail(s, PIC_EINVAL, "dims must be 1, 2 or 3");
+    if (!(g.dt > 0.0) || !std::isfinite(g.dt)) return fail(s, PIC_EINVAL, "dt must be positive");
+    if (g.precision != PIC_FP32 && g.precision != PIC_FP64) return fail(s, PIC_EINVAL, "precision");
+    if (g.sort_every < 1) g.sort_every = 20;
+    if (g.block == 0) g.block = 256;
+    if (g.block != 64 && g.block != 128 && g.block != 256 && g.block != 512)
+        return fail(s, PIC_EINVAL, "block must be 64, 128, 256 or 512");
+    if (g.series_cap <= 0) g.series_cap = 8192;
+    memset(&h, 0, sizeof(h));
+    h.dims = g.dims;
+    h.precision = g.precision;
+    s->es = g.precision == PIC_FP32 ? 4 : 8;
+    const int lim[3][3] = {{1 << 30, 1, 1}, {65535, 65535, 1}, {2047, 2047, 1023}};
+    for (int a = 0; a < 3; ++a) {
+        const bool act = a < g.dims;
+        if (!act) {
+            g.n[a] = 1;
+            g.tile[a] = 1;
+            g.bc[a] = PIC_PERIODIC;
+            if (!(g.dx[a] > 0.0)) g.dx[a] = 1.0;
+        }
+        if (g.n[a] < 1 || g.n[a] > lim[g.dims - 1][a]) return fail(s, PIC_EINVAL, "n[%d] out of range", a);
+        if (act && !(g.dx[a] > 0.0)) return fail(s, PIC_EINVAL, "dx[%d] must be positive", a);
+        if (g.bc[a] != PIC_PERIODIC && g.bc[a] != PIC_OPEN) return fail(s, PIC_EINVAL, "bc[%d]", a);
+        if (!pow2(g.tile[a])) return fail(s, PIC_EINVAL, "tile[%d] must be a power of two", a);
+        if (act && g.bc[a] == PIC_OPEN && g.n[a] < 4) return fail(s, PIC_EINVAL, "open axis %d needs >= 4 cells", a);
+        h.n[a] = g.n[a];
+        h.periodic[a] = g.bc[a] == PIC_PERIODIC ? 1 : 0;
+        h.L[a] = (act && !h.periodic[a]) ? g.n[a] + 1 : g.n[a];
+        h.T[a] = g.tile[a];
+        h.Tshift[a] = ilog2(g.tile[a]);
+        h.ntile[a] = (g.n[a] + g.tile[a] - 1) / g.tile[a];
+        if (act && h.periodic[a]) {
+            const long long lo_max = (long long)(h.ntile[a] - 1) * h.T[a];
+            if (2LL * g.n[a] <= lo_max + h.T[a] + 2)
+                return fail(s, PIC_EINVAL, "periodic axis %d too short for tile %d", a, h.T[a]);
+        }
+        h.Wf[a] = act ? h.T[a] + kGL + kGHf : 1;
+        h.Wj[a] = act ? h.T[a] + kGL + kGHj : 1;
+        h.gl[a] = act ? kGL : 0;
+        h.dx[a] = g.dx[a];
+        h.inv_dx[a] = 1.0 / g.dx[a];
+        h.dt_dx[a] = g.dt / g.dx[a];
+        h.mur_k[a] = (kC * g.dt - g.dx[a]) / (kC * g.dt + g.dx[a]);
+    }
+    // packed cell layout
+    const int sh[3][3] = {{0, 31, 31}, {0, 16, 31}, {0, 11, 22}};
+    const int mk[3][3] = {{0x7fffffff, 0, 0}, {0xffff, 0x7fff, 0}, {0x7ff, 0x7ff, 0x3ff}};
+    for (int a = 0; a < 3; ++a) {
+        h.pshift[a] = sh[g.dims - 1][a] >= 31 ? 0 : sh[g.dims - 1][a];
+        h.pmask[a] = mk[g.dims - 1][a];
+    }
+    long long tiles = 1;
+    for (int a = 0; a < 3; ++a) tiles *= h.ntile[a];
+    const long long keyspace = tiles * h.T[0] * h.T[1] * h.T[2];
+    if (keyspace >= (1LL << 31)) return fail(s, PIC_EINVAL, "cell key space exceeds int32");
+    h.ntiles = (int)tiles;
+    int bits = 1;
+    while ((1LL << bits) < keyspace) ++bits;
+    s->passes = (bits + 7) / 8;
+    h.Vf = h.Wf[0] * h.Wf[1] * h.Wf[2];
+    h.Vj = h.Wj[0] * h.Wj[1] * h.Wj[2];
+    const size_t plds = (size_t)s->es * (6 * (size_t)h.Vf + 3 * (size_t)h.Vj);
+    if (plds > 65536) return fail(s, PIC_EINVAL, "particle tile needs %zu bytes of LDS (> 64 KiB)", plds);
+    // field tiles
+    const int ft[3][3] = {{256, 1, 1}, {32, 8, 1}, {16, 4, 4}};
+    h.Lvol = 1;
+    h.nftiles = 1;
+    for (int a = 0; a < 3; ++a) {
+        h.FT[a] = a < g.dims ? ft[g.dims - 1][a] : 1;
+        h.nft[a] = (g.n[a] + h.FT[a] - 1) / h.FT[a];
+        h.nftiles *= h.nft[a];
+        h.Lvol *= h.L[a];
+    }
+    int fl = 1;
+    {
+        int ve = 1, vb = 1, vj = 1;
+        for (int a = 0; a < g.dims; ++a) { ve *= h.FT[a] + 3; vb *= h.FT[a] + 2; vj *= h.FT[a] + 1; }
+        fl = 3 * (ve + vb + 2 * vj);
+    }
+    s->field_lds = fl;
+    h.dt = g.dt;
+    h.series_cap = g.series_cap;
+    h.track = g.track_continuity ? 1 : 0;
+    h.src_kind = g.src_kind;
+    h.src_comp = g.src_comp;
+    h.src_axis = g.src_axis;
+    for (int a = 0; a < 3; ++a) h.src_index[a] = g.src_index[a];
+    h.src_j0 = g.src_j0;
+    h.src_omega = g.src_omega;
+    h.src_tau = g.src_tau;
+    if (g.src_kind != PIC_SRC_NONE) {
+        if (g.src_kind != PIC_SRC_SHEET && g.src_kind != PIC_SRC_POINT) return fail(s, PIC_EINVAL, "src_kind");
+        if (g.src_comp < 0 || g.src_comp > 2 || !(g.src_tau > 0.0)) return fail(s, PIC_EINVAL, "source");
+        if (g.src_kind == PIC_SRC_SHEET && (g.src_axis < 0 || g.src_axis >= g.dims)) return fail(s, PIC_EINVAL, "src_axis");
+        for (int a = 0; a < g.dims; ++a)
+            if ((g.src_kind == PIC_SRC_POINT || a == g.src_axis) && (g.src_index[a] < 0 || g.src_index[a] >= h.L[a]))
+                return fail(s, PIC_EINVAL, "source index out of the grid");
+    }
+    return PIC_OK;
+}
+
+// region membership of a cell: ball: all corners inside; box: cell inside (cell units)
+static bool cell_in_region(const pic_sim* s, const pic_species_desc& d, const int c[3])
+{
+    const int dims = s->g.dims;
+    if (d.region == PIC_REGION_ALL) return true;
+    if (d.region == PIC_REGION_BOX) {
+        for (int a = 0; a < dims; ++a)
+            if ((double)c[a] < d.rlo[a] || (double)(c[a] + 1) > d.rhi[a]) return false;
+        return true;
+    }
+    for (int corner = 0; corner < (1 << dims); ++corner) {
+        double r2 = 0.0;
+        for (int a = 0; a < dims; ++a) {
+            const double p = (double)(c[a] + ((corner >> a) & 1)) - d.rc[a];
+            r2 += p * p;
+        }
+        if (r2 > d.rr * d.rr) return false;
+    }
+    return true;
+}
+
+extern "C" int pic_create(const pic_grid_desc* g, pic_sim** out)
+{
+    if (!g || !out) { g_create_err = "null argument"; return PIC_EINVAL; }
+    *out = nullptr;
+    pic_sim* s = new (std::nothrow) pic_sim();
+    if (!s) { g_create_err = "out of host memory"; return PIC_ENOMEM; }
+    s->g = *g;
+    const int r = setup_grid(s);
+    if (r) {
+        g_create_err = s->err;
+        delete s;
+        return r;
+    }
+    g_create_err.clear();
+    *out = s;
+    return PIC_OK;
+}
+
+// plasma frequency squared of a species and its resonance, for eq:dtlimit
+static void species_freqs(const SpeciesHost& x, double& wp2, double& wb2)
+{
+    wp2 = x.density * x.d.q * x.d.q / (kEps0 * x.mass);
+    wb2 = 0.0;
+    if (x.d.kind == PIC_BOUND)
+        for (int a = 0; a < 3; ++a) wb2 = std::max(wb2, x.d.omega0[a] * x.d.omega0[a]);
+}
+
+extern "C" int pic_init_species(pic_sim* s, const pic_species_desc* d, uint64_t seed, int* species_id)
+{
+    if (!s || !d) return PIC_EINVAL;
+    if (s->bound) return fail(s, PIC_ESTATE, "species must be declared before pic_bind");
+    if ((int)s->sp.size() >= PIC_MAX_SPECIES) return fail(s, PIC_EINVAL, "too many species");
+    const int dims = s->g.dims;
+    SpeciesHost x;
+    x.d = *d;
+    x.seed = seed;
+    if (d->kind < PIC_FREE || d->kind > PIC_DIRAC) return fail(s, PIC_EINVAL, "species kind");
+    if (!(d->q != 0.0) || !std::isfinite(d->q)) return fail(s, PIC_EINVAL, "charge");
+    if (d->region < PIC_REGION_ALL || d->region > PIC_REGION_BOX) return fail(s, PIC_EINVAL, "region");
+    if (d->region == PIC_REGION_BALL)
+        for (int a = 1; a < dims; ++a)
+            if (s->g.dx[a] != s->g.dx[0]) return fail(s, PIC_EINVAL, "ball regions need equal cell sizes");
+    x.mass = d->m;
+    if (d->kind == PIC_DIRAC) {
+        if (!(d->v_f > 0.0)) return fail(s, PIC_EINVAL, "Dirac species needs v_f");
+        if (d->sheet_normal < -1 || d->sheet_normal > 2) return fail(s, PIC_EINVAL, "sheet_normal");
+        if (x.mass == 0.0) {
+            if (!(d->e_fermi > 0.0)) return fail(s, PIC_EINVAL, "Dirac mass needs e_fermi");
+            x.mass = dirac_mass(d->e_fermi, d->v_f);
+        }
+    }
+    if (!(x.mass > 0.0)) return fail(s, PIC_EINVAL, "mass must be positive");
+    if (d->momentum != PIC_MOM_COLD && d->momentum != PIC_MOM_FD) return fail(s, PIC_EINVAL, "momentum");
+    if (d->momentum == PIC_MOM_FD && d->kind == PIC_FREE && !(d->e_fermi > 0.0))
+        return fail(s, PIC_EINVAL, "FD momenta need e_fermi");
+    // particles stay inside: open axes need reflection into a region away from the faces, or a
+    // bound species, or the Dirac sheet normal
+    for (int a = 0; a < dims; ++a) {
+        if (s->g.bc[a] != PIC_OPEN) continue;
+        const bool pinned = d->kind == PIC_BOUND || (d->kind == PIC_DIRAC && d->sheet_normal == a);
+        if (!pinned && !(d->reflect && d->region != PIC_REGION_ALL))
+            return fail(s, PIC_EINVAL, "species %d can reach the open faces of axis %d", (int)s->sp.size(), a);
+        double lo, hi;
+        if (d->region == PIC_REGION_BALL) { lo = d->rc[a] - d->rr; hi = d->rc[a] + d->rr; }
+        else if (d->region == PIC_REGION_BOX) { lo = d->rlo[a]; hi = d->rhi[a]; }
+        else { lo = 0.0; hi = s->g.n[a]; }
+        if (lo < 3.0 || hi > s->g.n[a] - 3.0) return fail(s, PIC_EINVAL, "region within 3 cells of an open face");
+    }
+    if (d->count > 0) {
+        if (d->count >= (1LL << 31)) return fail(s, PIC_EINVAL, "count");
+        x.n = d->count;
+        x.weight = d->weight;
+        x.density = d->density;
+    } else {
+        if (d->ppc < 1) return fail(s, PIC_EINVAL, "ppc");
+        if (d->loading == PIC_LOAD_QUIET && dims != 1) return fail(s, PIC_EINVAL, "quiet start is 1D only");
+        int c[3];
+        for (c[2] = 0; c[2] < s->g.n[2]; ++c[2])
+            for (c[1] = 0; c[1] < s->g.n[1]; ++c[1])
+                for (c[0] = 0; c[0] < s->g.n[0]; ++c[0])
+                    if (cell_in_region(s, *d, c)) x.cells.push_back(pack_cell(s->h, c[0], c[1], c[2]));
+        x.n = (long long)x.cells.size() * d->ppc;
+        if (x.n >= (1LL << 31)) return fail(s, PIC_EINVAL, "too many particles");
+        double dens = d->density;
+        if (!(dens > 0.0)) {
+            if (!(d->e_fermi > 0.0)) return fail(s, PIC_EINVAL, "density or e_fermi required");
+            if (d->kind == PIC_DIRAC) dens = dirac_density2d(d->e_fermi, d->v_f) / s->g.dx[d->sheet_normal >= 0 ? d->sheet_normal : 0];
+            else dens = density_from_fermi(d->e_fermi, x.mass);
+        }
+        x.density = dens;
+        double dv = 1.0;
+        for (int a = 0; a < dims; ++a) dv *= s->g.dx[a];
+        x.weight = dens * dv / d->ppc;
+        if (d->kind == PIC_FREE && d->momentum == PIC_MOM_FD && d->temperature > 0.0) {
+            // inverse-CDF table of eq:fddist on x = sqrt(e/e_max), e_max = mu + 40 kT
+            const double mu = d->e_fermi, kT = kKb * d->temperature;
+            x.e_max = mu + 40.0 * kT;
+            x.cdf.resize(kFdTab + 1);
+            double prev = 0.0;
+            x.cdf[0] = 0.0;
+            for (int k = 1; k <= kFdTab; ++k) {
+                const double xx = (double)k / (double)kFdTab;
+                const double e = x.e_max * xx * xx;
+                const double p = xx * xx / (1.0 + std::exp((e - mu) / kT));
+                x.cdf[k] = x.cdf[k - 1] + 0.5 * (prev + p) * (1.0 / (double)kFdTab);
+                prev = p;
+            }
+            const double tot = x.cdf[kFdTab];
+            for (auto& v : x.cdf) v /= tot;
+        }
+    }
+    // eq:dtlimit with all declared species (plasma frequencies add, largest resonance)
+    {
+        double wp2 = 0.0, wb2 = 0.0;
+        std::vector<SpeciesHost*> all;
+        for (auto& y : s->sp) all.push_back(&y);
+        all.push_back(&x);
+        for (auto* y : all) {
+            double a, b;
+            species_freqs(*y, a, b);
+            wp2 += a;
+            wb2 = std::max(wb2, b);
+        }
+        double cs = 0.0;
+        for (int a = 0; a < dims; ++a) cs += 1.0 / (s->g.dx[a] * s->g.dx[a]);
+        const double lim = 1.0 / std::sqrt(0.25 * wb2 + 0.25 * wp2 + kC * kC * cs);
+        if (!(s->g.dt < lim)) return fail(s, PIC_ECFL, "dt %.6e is not below the stability limit %.6e", s->g.dt, lim);
+    }
+    const int sid = (int)s->sp.size();
+    s->sp.push_back(std::move(x));
+    if (species_id) *species_id = sid;
+    return PIC_OK;
+}
+
+// tiles that can ever hold particles of any species (sizes the slot array)
+static int count_slot_tiles(const pic_sim* s)
+{
+    const SimDev& h = s->h;
+    std::vector<char> mark(h.ntiles, 0);
+    const int dims = s->g.dims;
+    for (const auto& x : s->sp) {
+        double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+        bool all = false;
+        const auto& d = x.d;
+        for (int a = 0; a < dims; ++a) {
+            if (d.region == PIC_REGION_ALL) { all = true; break; }
+            double l, u;
+            if (d.region == PIC_REGION_BALL) { l = d.rc[a] - d.rr; u = d.rc[a] + d.rr; }
+            else { l = d.rlo[a]; u = d.rhi[a]; }
+            const bool pinned = d.kind == PIC_BOUND || (d.kind == PIC_DIRAC && d.sheet_normal == a);
+            if (!pinned && !d.reflect) { l = 0; u = s->g.n[a]; }
+            lo[a] = l - 2.0;
+            hi[a] = u + 2.0;
+        }
+        if (all || d.count > 0) {
+            std::fill(mark.begin(), mark.end(), 1);
+            continue;
+        }
+        int t0[3] = {0, 0, 0}, t1[3] = {0, 0, 0};
+        for (int a = 0; a < 3; ++a) {
+            if (a >= dims) continue;
+            t0[a] = (int)std::floor(lo[a] / h.T[a]);
+            t1[a] = (int)std::floor(hi[a] / h.T[a]);
+        }
+        for (int z = t0[2]; z <= t1[2]; ++z)
+            for (int y = t0[1]; y <= t1[1]; ++y)
+                for (int xx = t0[0]; xx <= t1[0]; ++xx) {
+                    int t[3] = {xx, y, z};
+                    for (int a = 0; a < dims; ++a) t[a] = ((t[a] % h.ntile[a]) + h.ntile[a]) % h.ntile[a];
+                    mark[(t[2] * h.ntile[1] + t[1]) * h.ntile[0] + t[0]] = 1;
+                }
+    }
+    int n = 0;
+    for (char m : mark) n += m;
+    return std::max(n, 1);
+}
+
+// Bump allocator over the arena: assign == false only measures.
+struct Planner {
+    char* base;
+    size_t off = 0;
+    bool assign;
+    template <typename T>
+    T* take(size_t count)
+    {
+        off = (off + kAlign - 1) / kAlign * kAlign;
+        T* p = assign ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += sizeof(T) * (count ? count : 1);
+        return p;
+    }
+    void* takeb(size_t bytes)
+    {
+        off = (off + kAlign - 1) / kAlign * kAlign;
+        void* p = assign ? base + off : nullptr;
+        off += bytes ? bytes : 1;
+        return p;
+    }
+};
+
+static size_t plan(pic_sim* s, char* base, bool assign)
+{
+    SimDev& h = s->h;
+    Planner P{base, 0, assign};
+    const size_t es = s->es;
+    const size_t L = (size_t)h.Lvol;
+    s->d = P.take<SimDev>(1);
+    for (int c = 0; c < 3; ++c) h.E[c] = P.takeb(L * es);
+    for (int c = 0; c < 3; ++c) h.B[c] = P.takeb(L * es);
+    for (int p = 0; p < 2; ++p) h.jover[p] = P.takeb(3 * L * es);
+    s->max_slots = count_slot_tiles(s);
+    h.max_slots = s->max_slots;
+    h.slots = P.takeb((size_t)s->max_slots * 3 * h.Vj * es);
+    h.tile_slot = P.take<int>(h.ntiles);
+    h.active = P.take<int>(h.ntiles);
+    h.n_active = P.take<int>(1);
+    h.step_p = P.take<long long>(1);
+    h.step_f = P.take<long long>(1);
+    h.over_stamp = P.take<long long>(2);
+    h.over_count = P.take<unsigned long long>(1);
+    h.partials = P.take<double>((size_t)s->max_slots * 3);
+    h.series = P.take<double>((size_t)h.series_cap * 3);
+    h.rho_ion = P.take<double>(L);
+    h.rho_a = P.take<double>(L);
+    h.rho_b = P.take<double>(L);
+    h.jtrack = h.track ? P.takeb(3 * L * es) : nullptr;
+    h.red = P.take<double>(16);
+    s->part = P.take<double>(kDiagBlocks * 4);
+    s->outv = P.take<double>(16);
+    s->cont = P.take<double>(2);
+    long long nmax = 1;
+    for (auto& x : s->sp) nmax = std::max(nmax, x.n);
+    const long long nb = (nmax + kSortIpb - 1) / kSortIpb;
+    h.sort_hist = P.take<int>((size_t)256 * nb);
+    h.nspecies = (int)s->sp.size();
+    for (size_t i = 0; i < s->sp.size(); ++i) {
+        SpeciesHost& x = s->sp[i];
+        SpeciesDev& d = h.sp[i];
+        const size_t n = (size_t)x.n;
+        const bool bound = x.d.kind == PIC_BOUND;
+        for (int k = 0; k < 2; ++k) {
+            x.cell[k] = P.take<int>(n);
+            for (int a = 0; a < 3; ++a) {
+                x.off[k][a] = a < s->g.dims ? P.takeb(n * es) : nullptr;
+                x.v[k][a] = P.takeb(n * es);
+                x.xi[k][a] = bound ? P.takeb(n * es) : nullptr;
+            }
+        }
+        d.keys = P.take<int>(n);
+        d.keys_alt = P.take<int>(n);
+        d.vals = P.take<int>(n);
+        d.vals_alt = P.take<int>(n);
+        d.tile_start = P.take<int>((size_t)h.ntiles + 1);
+        x.dcells = x.cells.empty() ? nullptr : P.take<int>(x.cells.size());
+        x.dcdf = x.cdf.empty() ? nullptr : P.take<double>(x.cdf.size());
+    }
+    return P.off + kAlign;
+}
+
+// Fill the host mirror of species i from the host state (current parity).
+static void mirror_species(pic_sim* s, int i)
+{
+    SpeciesHost& x = s->sp[i];
+    SpeciesDev& d = s->h.sp[i];
+    const auto& D = x.d;
+    d.kind = D.kind;
+    d.reflect = D.reflect ? 1 : 0;
+    d.region = D.region;
+    d.sheet_normal = D.kind == PIC_DIRAC ? D.sheet_normal : -1;
+    d.n = (int)x.n;
+    d.sortable = 1;
+    d.qm = D.q / x.mass;
+    d.qw = D.q * x.weight;
+    d.mw = x.mass * x.weight;
+    for (int a = 0; a < 3; ++a) {
+        d.w2[a] = D.kind == PIC_BOUND ? D.omega0[a] * D.omega0[a] : 0.0;
+        d.gam[a] = D.kind == PIC_BOUND ? D.gamma[a] : 0.0;
+        d.rc[a] = D.rc[a];
+        d.rlo[a] = D.rlo[a];
+        d.rhi[a] = D.rhi[a];
+    }
+    d.rr = D.rr;
+    d.bw = D.kind == PIC_BOUND ? D.b_weight : 0.0;
+    d.vf = D.v_f;
+    const int p = x.parity, q = 1 - p;
+    d.cell = x.cell[p];
+    d.cell_alt = x.cell[q];
+    for (int a = 0; a < 3; ++a) {
+        d.off[a] = x.off[p][a];
+        d.off_alt[a] = x.off[q][a];
+        d.v[a] = x.v[p][a];
+        d.v_alt[a] = x.v[q][a];
+        d.xi[a] = x.xi[p][a];
+        d.xi_alt[a] = x.xi[q][a];
+    }
+}
+
+static int upload_table(pic_sim* s)
+{
+    for (size_t i = 0; i < s->sp.size(); ++i) mirror_species(s, (int)i);
+    HIPCHK(s, hipMemcpyAsync(s->d, &s->h, sizeof(SimDev), hipMemcpyHostToDevice, s->st));
+    return PIC_OK;
+}
+
+extern "C" int pic_footprint(const pic_sim* s, size_t* bytes)
+{
+    if (!s || !bytes) return PIC_EINVAL;
+    pic_sim tmp = *s;  // plan on a copy: measuring assigns nothing
+    tmp.gexec = nullptr;
+    *bytes = plan(&tmp, nullptr, false);
+    return PIC_OK;
+}
+
+static hipError_t launch_load(pic_sim* s, int i)
+{
+    SpeciesHost& x = s->sp[i];
+    LoadArgs A{};
+    A.s = i;
+    A.sid = i;
+    A.ppc = x.d.ppc;
+    A.ncell = (int)x.cells.size();
+    A.momentum = x.d.momentum;
+    A.loading = x.d.loading;
+    A.pert_mode = x.d.pert_mode;
+    A.ntab = kFdTab;
+    A.seed = x.seed;
+    A.e_fermi = x.d.e_fermi;
+    A.kT = (x.d.kind == PIC_FREE && x.d.momentum == PIC_MOM_FD) ? kKb * x.d.temperature : 0.0;
+    A.mass = x.mass;
+    A.pert_amp = x.d.pert_amp;
+    A.xi_radius = x.d.xi_radius;
+    A.e_max = x.e_max;
+    A.cells = x.dcells;
+    A.cdf = x.dcdf;
+    if (s->g.precision == PIC_FP32) return Launchers<float>::load(s->g.dims, s->d, A, s->st);
+    return Launchers<double>::load(s->g.dims, s->d, A, s->st);
+}
+
+extern "C" int pic_bind(pic_sim* s, void* dev_arena, size_t bytes, void* hip_stream)
+{
+    if (!s) return PIC_EINVAL;
+    if (s->bound) return fail(s, PIC_ESTATE, "already bound");
+    if (!dev_arena) return fail(s, PIC_EINVAL, "null arena");
+    if (reinterpret_cast<uintptr_t>(dev_arena) % kAlign) return fail(s, PIC_EINVAL, "arena must be 256-byte aligned");
+    size_t need = 0;
+    pic_footprint(s, &need);
+    if (bytes < need) return fail(s, PIC_ENOMEM, "arena of %zu bytes is smaller than the footprint %zu", bytes, need);
+    s->arena = reinterpret_cast<char*>(dev_arena);
+    s->arena_bytes = bytes;
+    s->st = reinterpret_cast<hipStream_t>(hip_stream);
+    plan(s, s->arena, true);
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
+    }
+    s->pgrid = std::max(1, std::min(s->max_slots, ncu * 8));
+    HIPCHK(s, enqueue_fill(s->arena, need - kAlign, s->st));
+    int r = upload_table(s);
+    if (r) return r;
+    for (size_t i = 0; i < s->sp.size(); ++i) {
+        SpeciesHost& x = s->sp[i];
+        if (x.d.count > 0 || x.n == 0) continue;
+        HIPCHK(s, hipMemcpyAsync(x.dcells, x.cells.data(), x.cells.size() * sizeof(int), hipMemcpyHostToDevice, s->st));
+        if (x.dcdf)
+            HIPCHK(s, hipMemcpyAsync(x.dcdf, x.cdf.data(), x.cdf.size() * sizeof(double), hipMemcpyHostToDevice, s->st));
+        HIPCHK(s, launch_load(s, (int)i));
+    }
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    s->bound = true;
+    s->need_sort = true;
+    s->step = 0;
+    return PIC_OK;
+}
+
+extern "C" int pic_field_shape(const pic_sim* s, int L[3])
+{
+    if (!s || !L) return PIC_EINVAL;
+    for (int a = 0; a < 3; ++a) L[a] = s->h.L[a];
+    return PIC_OK;
+}
+
+extern "C" long long pic_species_count(const pic_sim* s, int sid)
+{
+    if (!s || sid < 0 || sid >= (int)s->sp.size()) return -1;
+    return s->sp[sid].n;
+}
+
+template <typename R>
+static void to_real(const double* src, size_t n, std::vector<char>& buf)
+{
+    buf.resize(n * sizeof(R));
+    R* d = reinterpret_cast<R*>(buf.data());
+    for (size_t i = 0; i < n; ++i) d[i] = R(src[i]);
+}
+
+extern "C" int pic_load_particles(pic_sim* s, int sid, const double* x, const double* v, const double* xi, size_t n)
+{
+    if (!s) return PIC_EINVAL;
+    if (!s->bound) return fail(s, PIC_ESTATE, "bind before loading particles");
+    if (s->batch_refs) return fail(s, PIC_ESTATE, "simulation is in a batch");
+    if (sid < 0 || sid >= (int)s->sp.size()) return fail(s, PIC_EINVAL, "species id");
+    SpeciesHost& sp = s->sp[sid];
+    if ((long long)n != sp.n) return fail(s, PIC_EINVAL, "n = %zu but the species holds %lld", n, sp.n);
+    if (!x || !v) return fail(s, PIC_EINVAL, "null x or v");
+    const bool bound = sp.d.kind == PIC_BOUND;
+    if (bound && !xi) return fail(s, PIC_EINVAL, "bound species need xi");
+    const int dims = s->g.dims;
+    std::vector<int> cell(n);
+    std::vector<double> off[3], vv[3], xx[3];
+    for (int a = 0; a < 3; ++a) { off[a].resize(n); vv[a].resize(n); xx[a].resize(bound ? n : 0); }
+    for (size_t i = 0; i < n; ++i) {
+        int c[3] = {0, 0, 0};
+        for (int a = 0; a < 3; ++a) {
+            if (!std::isfinite(x[3 * i + a]) || !std::isfinite(v[3 * i + a]) || (bound && !std::isfinite(xi[3 * i + a])))
+                return fail(s, PIC_EINVAL, "non-finite input at particle %zu", i);
+            vv[a][i] = v[3 * i + a];
+            if (bound) xx[a][i] = xi[3 * i + a];
+            if (a >= dims) continue;
+            double X = x[3 * i + a] / s->g.dx[a];
+            const double nn = (double)s->g.n[a];
+            if (s->h.periodic[a]) {
+                if (X >= nn) X -= nn;
+                else if (X < 0.0) { X += nn; if (X >= nn) X = 0.0; }
+            }
+            double f = std::floor(X);
+            double o = X - f;
+            int ci = (int)f;
+            if (o >= 1.0) { o = 0.0; ci += 1; }
+            if (ci < 0 || ci >= s->g.n[a]) return fail(s, PIC_EINVAL, "particle %zu outside the grid", i);
+            c[a] = ci;
+            off[a][i] = o;
+        }
+        cell[i] = pack_cell(s->h, c[0], c[1], c[2]);
+    }
+    const int p = sp.parity;
+    HIPCHK(s, hipMemcpyAsync(sp.cell[p], cell.data(), n * sizeof(int), hipMemcpyHostToDevice, s->st));
+    std::vector<char> buf;
+    auto put = [&](void* dst, const std::vector<double>& src) -> hipError_t {
+        if (s->es == 4) to_real<float>(src.data(), n, buf); else to_real<double>(src.data(), n, buf);
+        hipError_t e = hipMemcpyAsync(dst, buf.data(), buf.size(), hipMemcpyHostToDevice, s->st);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(s->st);
+    };
+    for (int a = 0; a < 3; ++a) {
+        if (a < dims) HIPCHK(s, put(sp.off[p][a], off[a]));
+        HIPCHK(s, put(sp.v[p][a], vv[a]));
+        if (bound) HIPCHK(s, put(sp.xi[p][a], xx[a]));
+    }
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    s->need_sort = true;
+    sp.sorted_once = false;
+    return PIC_OK;
+}
+
+extern "C" int pic_load_fields(pic_sim* s, const double* e, const double* b)
+{
+    if (!s) return PIC_EINVAL;
+    if (!s->bound) return fail(s, PIC_ESTATE, "bind before loading fields");
+    const size_t L = (size_t)s->h.Lvol;
+    std::vector<char> buf;
+    for (int c = 0; c < 3; ++c) {
+        for (int w = 0; w < 2; ++w) {
+            const double* src = w == 0 ? e : b;
+            if (!src) continue;
+            if (s->es == 4) to_real<float>(src + c * L, L, buf); else to_real<double>(src + c * L, L, buf);
+            HIPCHK(s, hipMemcpyAsync(w == 0 ? s->h.E[c] : s->h.B[c], buf.data(), buf.size(), hipMemcpyHostToDevice, s->st));
+            HIPCHK(s, hipStreamSynchronize(s->st));
+        }
+    }
+    return PIC_OK;
+}
+
+static hipError_t launch_rho(pic_sim* s, double* rho)
+{
+    hipError_t e = enqueue_fill(rho, sizeof(double) * (size_t)s->h.Lvol, s->st);
+    if (e != hipSuccess) return e;
+    if (s->g.precision == PIC_FP32) return Launchers<float>::rho(s->g.dims, dtab(s), rho, kDiagBlocks, s->st);
+    return Launchers<double>::rho(s->g.dims, dtab(s), rho, kDiagBlocks, s->st);
+}
+
+extern "C" int pic_init_fields(pic_sim* s, int mode)
+{
+    if (!s) return PIC_EINVAL;
+    if (!s->bound) return fail(s, PIC_ESTATE, "bind first");
+    if (s->batch_refs) return fail(s, PIC_ESTATE, "simulation is in a batch");
+    if (mode < 0 || mode > 2) return fail(s, PIC_EINVAL, "mode");
+    if (mode == 2 && !(s->g.dims == 1 && s->h.periodic[0])) return fail(s, PIC_EINVAL, "Gauss initialisation is 1D periodic only");
+    HIPCHK(s, launch_rho(s, s->h.rho_a));
+    if (mode == 0) {
+        HIPCHK(s, enqueue_ion(s->d, s->h.rho_a, 0, nullptr, s->st));
+    } else {
+        HIPCHK(s, enqueue_sum(s->h.rho_a, s->h.Lvol, s->part, kDiagBlocks, s->st));
+        HIPCHK(s, enqueue_final(s->part, kDiagBlocks, 1, 0, s->outv, s->st));
+        HIPCHK(s, enqueue_ion(s->d, s->h.rho_a, 1, s->outv, s->st));
+    }
+    if (mode == 2) {
+        if (s->g.precision == PIC_FP32) HIPCHK(s, Launchers<float>::gauss_init_1d(s->d, s->h.rho_a, s->st));
+        else HIPCHK(s, Launchers<double>::gauss_init_1d(s->d, s->h.rho_a, s->st));
+    }
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return PIC_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Step
+// ---------------------------------------------------------------------------------------------
+static int enqueue_sort_all(pic_sim* s, std::vector<int>* sorted)
+{
+    for (size_t i = 0; i < s->sp.size(); ++i) {
+        SpeciesHost& x = s->sp[i];
+        if (x.d.kind == PIC_BOUND && x.sorted_once) continue;  // anchors never move
+        if (x.n > 0) {
+            HIPCHK(s, enqueue_sort(s->d, (int)i, (int)x.n, s->passes, s->es, s->st));
+            x.parity ^= 1;
+        }
+        HIPCHK(s, enqueue_ranges(s->d, (int)i, s->h.ntiles, s->passes, s->st));
+        x.sorted_once = true;
+        if (sorted) sorted->push_back((int)i);
+    }
+    HIPCHK(s, enqueue_compact(s->d, s->st));
+    s->need_sort = false;
+    return PIC_OK;
+}
+
+static Launch make_launch(pic_sim* s)
+{
+    Launch L{};
+    L.sims = s->d;
+    L.nsims = 1;
+    L.max_vf = s->h.Vf;
+    L.max_vj = s->h.Vj;
+    L.pgrid = s->pgrid;
+    L.block = s->g.block;
+    L.ftiles_total = s->h.nftiles;
+    L.stream = s->st;
+    return L;
+}
+
+static int enqueue_push_fields(pic_sim* s)
+{
+    const Launch L = make_launch(s);
+    if (s->g.precision == PIC_FP32) {
+        HIPCHK(s, Launchers<float>::particles(s->g.dims, L));
+        HIPCHK(s, Launchers<float>::fields(s->g.dims, L, s->field_lds));
+    } else {
+        HIPCHK(s, Launchers<double>::particles(s->g.dims, L));
+        HIPCHK(s, Launchers<double>::fields(s->g.dims, L, s->field_lds));
+    }
+    return PIC_OK;
+}
+
+static int enqueue_one_step(pic_sim* s)
+{
+    int r;
+    if (s->need_sort || s->step % s->g.sort_every == 0)
+        if ((r = enqueue_sort_all(s, nullptr))) return r;
+    if (s->h.track) HIPCHK(s, launch_rho(s, s->h.rho_a));
+    if ((r = enqueue_push_fields(s))) return r;
+    if (s->h.track) {
+        HIPCHK(s, launch_rho(s, s->h.rho_b));
+        if (s->g.precision == PIC_FP32) HIPCHK(s, Launchers<float>::continuity(s->g.dims, s->d, s->part, kDiagBlocks, s->st));
+        else HIPCHK(s, Launchers<double>::continuity(s->g.dims, s->d, s->part, kDiagBlocks, s->st));
+        HIPCHK(s, enqueue_final(s->part, kDiagBlocks, 2, 1, s->cont, s->st));
+    }
+    s->step++;
+    return PIC_OK;
+}
+
+static void drop_graph(pic_sim* s)
+{
+    if (s->gexec) {
+        (void)hipGraphExecDestroy(s->gexec);
+        s->gexec = nullptr;
+    }
+}
+
+extern "C" int pic_use_graphs(pic_sim* s, int on)
+{
+    if (!s) return PIC_EINVAL;
+    s->graphs = on != 0;
+    if (!s->graphs) drop_graph(s);
+    return PIC_OK;
+}
+
+// capture one sort period (sort + sort_every steps) starting at a multiple of sort_every
+static int capture_period(pic_sim* s)
+{
+    drop_graph(s);
+    const long long step0 = s->step;
+    std::vector<int> par;
+    for (auto& x : s->sp) par.push_back(x.parity);
+    if (!s->st) return fail(s, PIC_EINVAL, "graphs need a non-default stream");
+    HIPCHK(s, hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
+    int r = PIC_OK;
+    s->graph_species.clear();
+    r = enqueue_sort_all(s, &s->graph_species);
+    for (int k = 0; k < s->g.sort_every && !r; ++k) r = enqueue_push_fields(s);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s->st, &graph);
+    // capture does not execute: restore the host view of the state
+    s->step = step0;
+    for (size_t i = 0; i < s->sp.size(); ++i) s->sp[i].parity = par[i];
+    if (r) { if (graph) (void)hipGraphDestroy(graph); return r; }
+    if (e != hipSuccess) return fail(s, PIC_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&s->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) { s->gexec = nullptr; return fail(s, PIC_EDEVICE, "graph instantiate: %s", hipGetErrorString(e)); }
+    return PIC_OK;
+}
+
+extern "C" int pic_step(pic_sim* s, int nsteps)
+{
+    if (!s) return PIC_EINVAL;
+    if (!s->bound) return fail(s, PIC_ESTATE, "bind before stepping");
+    if (s->batch_refs) return fail(s, PIC_ESTATE, "simulation is in a batch; use pic_batch_step");
+    if (nsteps < 0) return fail(s, PIC_EINVAL, "nsteps");
+    int r;
+    while (nsteps > 0) {
+        const int P = s->g.sort_every;
+        const bool bound_sorted = [&] {
+            for (auto& x : s->sp) if (x.d.kind == PIC_BOUND && !x.sorted_once) return false;
+            return true;
+        }();
+        if (s->graphs && s->st && !s->h.track && !s->need_sort && bound_sorted && s->step % P == 0 && nsteps >= P) {
+            if (!s->gexec && (r = capture_period(s))) return r;
+            HIPCHK(s, hipGraphLaunch(s->gexec, s->st));
+            for (int i : s->graph_species) s->sp[i].parity ^= 1;
+            s->step += P;
+            nsteps -= P;
+            continue;
+        }
+        if ((r = enqueue_one_step(s))) return r;
+        --nsteps;
+    }
+    return PIC_OK;
+}
+
+extern "C" int pic_sync(pic_sim* s)
+{
+    if (!s) return PIC_EINVAL;
+    if (!s->bound) return PIC_OK;
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return PIC_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Diagnostics
+// ---------------------------------------------------------------------------------------------
+template <typename R>
+static void from_real(const std::vector<char>& buf, size_t n, double* dst, size_t stride)
+{
+    const R* p = reinterpret_cast<const R*>(buf.data());
+    for (size_t i = 0; i < n; ++i) dst[i * stride] = double(p[i]);
+}
+
+static int fetch_real(pic_sim* s, const void* src, size_t n, double* dst, size_t stride)
+{
+    std::vector<char> buf(n * s->es);
+    if (n) {
+        HIPCHK(s, hipMemcpyAsync(buf.data(), src, buf.size(), hipMemcpyDeviceToHost, s->st));
+        HIPCHK(s, hipStreamSynchronize(s->st));
+    }
+    if (s->es == 4) from_real<float>(buf, n, dst, stride); else from_real<double>(buf, n, dst, stride);
+    return PIC_OK;
+}
+
+static int fetch_doubles(pic_sim* s, const double* src, size_t n, double* dst)
+{
+    HIPCHK(s, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return PIC_OK;
+}
+
+extern "C" int pic_diag(pic_sim* s, int kind, int arg, double* out, size_t cap, size_t* n_out)
+{
+    if (!s) return PIC_EINVAL;
+    if (!s->bound) return fail(s, PIC_ESTATE, "bind first");
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    const bool f32 = s->g.precision == PIC_FP32;
+    const size_t L = (size_t)s->h.Lvol;
+    const int nsp = (int)s->sp.size();
+    size_t need = 0;
+    switch (kind) {
+    case PIC_DIAG_FIELD_ENERGY: case PIC_DIAG_STEP: case PIC_DIAG_OVERFLOW: need = 1; break;
+    case PIC_DIAG_KINETIC_ENERGY: need = arg < 0 ? nsp : 1; break;
+    case PIC_DIAG_GAUSS_RESIDUAL: case PIC_DIAG_CONTINUITY: need = 2; break;
+    case PIC_DIAG_CURRENT_SERIES: need = 3 * (size_t)std::min<long long>(s->step, s->h.series_cap); break;
+    case PIC_DIAG_PARTICLE_COUNT: need = nsp; break;
+    case PIC_DIAG_EXPORT_PARTICLES: case PIC_DIAG_KEYS:
+        if (arg < 0 || arg >= nsp) return fail(s, PIC_EINVAL, "species id");
+        need = (kind == PIC_DIAG_KEYS ? 1 : 9) * (size_t)s->sp[arg].n;
+        break;
+    case PIC_DIAG_EXPORT_FIELDS: need = 6 * L; break;
+    case PIC_DIAG_EXPORT_CURRENT:
+        if (!s->h.track) return fail(s, PIC_EINVAL, "current export needs track_continuity");
+        need = 3 * L;
+        break;
+    default: return fail(s, PIC_EINVAL, "unknown diagnostic %d", kind);
+    }
+    if (n_out) *n_out = need;
+    if (!out || cap < need) return fail(s, PIC_ETRUNC, "output needs %zu values", need);
+    switch (kind) {
+    case PIC_DIAG_FIELD_ENERGY: {
+        if (f32) HIPCHK(s, Launchers<float>::field_energy(dtab(s), s->part, kDiagBlocks, s->st));
+        else HIPCHK(s, Launchers<double>::field_energy(dtab(s), s->part, kDiagBlocks, s->st));
+        HIPCHK(s, enqueue_final(s->part, kDiagBlocks, 1, 0, s->outv, s->st));
+        int r = fetch_doubles(s, s->outv, 1, out);
+        if (r) return r;
+        if (!std::isfinite(out[0])) return fail(s, PIC_ENONFINITE, "non-finite field energy");
+        return PIC_OK;
+    }
+    case PIC_DIAG_KINETIC_ENERGY: {
+        for (int i = 0; i < nsp; ++i) {
+            if (arg >= 0 && i != arg) continue;
+            if (f32) HIPCHK(s, Launchers<float>::kinetic(dtab(s), i, s->part, kDiagBlocks, s->st));
+            else HIPCHK(s, Launchers<double>::kinetic(dtab(s), i, s->part, kDiagBlocks, s->st));
+            HIPCHK(s, enqueue_final(s->part, kDiagBlocks, 1, 0, s->outv, s->st));
+            int r = fetch_doubles(s, s->outv, 1, out + (arg >= 0 ? 0 : i));
+            if (r) return r;
+            if (!std::isfinite(out[arg >= 0 ? 0 : i])) return fail(s, PIC_ENONFINITE, "non-finite kinetic energy");
+        }
+        return PIC_OK;
+    }
+    case PIC_DIAG_GAUSS_RESIDUAL: {
+        HIPCHK(s, launch_rho(s, s->h.rho_b));
+        if (f32) HIPCHK(s, Launchers<float>::gauss(s->g.dims, dtab(s), s->h.rho_b, s->part, kDiagBlocks, s->st));
+        else HIPCHK(s, Launchers<double>::gauss(s->g.dims, dtab(s), s->h.rho_b, s->part, kDiagBlocks, s->st));
+        HIPCHK(s, enqueue_final(s->part, kDiagBlocks, 2, 1, s->outv, s->st));
+        return fetch_doubles(s, s->outv, 2, out);
+    }
+    case PIC_DIAG_CONTINUITY: return fetch_doubles(s, s->cont, 2, out);
+    case PIC_DIAG_CURRENT_SERIES: return need ? fetch_doubles(s, s->h.series, need, out) : PIC_OK;
+    case PIC_DIAG_PARTICLE_COUNT:
+        for (int i = 0; i < nsp; ++i) out[i] = (double)s->sp[i].n;
+        return PIC_OK;
+    case PIC_DIAG_STEP: out[0] = (double)s->step; return PIC_OK;
+    case PIC_DIAG_OVERFLOW: {
+        unsigned long long c = 0;
+        HIPCHK(s, hipMemcpyAsync(&c, s->h.over_count, sizeof(c), hipMemcpyDeviceToHost, s->st));
+        HIPCHK(s, hipStreamSynchronize(s->st));
+        out[0] = (double)c;
+        return PIC_OK;
+    }
+    case PIC_DIAG_EXPORT_PARTICLES: {
+        SpeciesHost& x = s->sp[arg];
+        const size_t n = (size_t)x.n;
+        const int p = x.parity;
+        std::vector<int> cell(n);
+        if (n) {
+            HIPCHK(s, hipMemcpyAsync(cell.data(), x.cell[p], n * sizeof(int), hipMemcpyDeviceToHost, s->st));
+            HIPCHK(s, hipStreamSynchronize(s->st));
+        }
+        double* X = out;
+        double* V = out + 3 * n;
+        double* XI = out + 6 * n;
+        std::fill(out, out + 9 * n, 0.0);
+        int r;
+        for (int a = 0; a < 3; ++a) {
+            if (a < s->g.dims && (r = fetch_real(s, x.off[p][a], n, X + a, 3))) return r;
+            if ((r = fetch_real(s, x.v[p][a], n, V + a, 3))) return r;
+            if (x.d.kind == PIC_BOUND && (r = fetch_real(s, x.xi[p][a], n, XI + a, 3))) return r;
+        }
+        for (size_t i = 0; i < n; ++i) {
+            int c[3];
+            unpack_cell(s->h, cell[i], c);
+            for (int a = 0; a < 3; ++a)
+                X[3 * i + a] = a < s->g.dims ? ((double)c[a] + X[3 * i + a]) * s->g.dx[a] : 0.0;
+        }
+        return PIC_OK;
+    }
+    case PIC_DIAG_EXPORT_FIELDS: {
+        int r;
+        for (int c = 0; c < 3; ++c) {
+            if ((r = fetch_real(s, s->h.E[c], L, out + c * L, 1))) return r;
+            if ((r = fetch_real(s, s->h.B[c], L, out + (3 + c) * L, 1))) return r;
+        }
+        return PIC_OK;
+    }
+    case PIC_DIAG_EXPORT_CURRENT: {
+        int r;
+        for (int c = 0; c < 3; ++c)
+            if ((r = fetch_real(s, static_cast<char*>(s->h.jtrack) + c * L * s->es, L, out + c * L, 1))) return r;
+        return PIC_OK;
+    }
+    case PIC_DIAG_KEYS: {
+        const size_t n = (size_t)s->sp[arg].n;
+        std::vector<int> k(n);
+        HIPCHK(s, enqueue_keys_only(dtab(s), arg, (int)n, s->st));
+        if (n) {
+            HIPCHK(s, hipMemcpyAsync(k.data(), s->h.sp[arg].keys, n * sizeof(int), hipMemcpyDeviceToHost, s->st));
+            HIPCHK(s, hipStreamSynchronize(s->st));
+        }
+        for (size_t i = 0; i < n; ++i) out[i] = (double)k[i];
+        return PIC_OK;
+    }
+    }
+    return PIC_EINVAL;
+}
+
+extern "C" const char* pic_last_error(const pic_sim* s)
+{
+    return s ? s->err.c_str() : g_create_err.c_str();
+}
+
+extern "C" void pic_destroy(pic_sim* s)
+{
+    if (!s) return;
+    drop_graph(s);
+    delete s;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Batched form
+// ---------------------------------------------------------------------------------------------
+static int bfail(pic_batch* b, int code, const char* msg)
+{
+    if (b) b->err = msg;
+    return code;
+}
+
+extern "C" int pic_batch_footprint(int max_sims, int dims, size_t* bytes)
+{
+    if (!bytes || max_sims < 1 || max_sims > MAX_BATCH || dims < 1 || dims > 3) return PIC_EINVAL;
+    *bytes = sizeof(SimDev) * (size_t)max_sims + kAlign;
+    return PIC_OK;
+}
+
+extern "C" int pic_batch_create(int max_sims, int dims, int precision, void* dev_arena, size_t bytes,
+                                void* hip_stream, pic_batch** out)
+{
+    if (!out) return PIC_EINVAL;
+    *out = nullptr;
+    size_t need = 0;
+    if (pic_batch_footprint(max_sims, dims, &need)) return PIC_EINVAL;
+    if (!dev_arena || bytes < need || reinterpret_cast<uintptr_t>(dev_arena) % kAlign) return PIC_ENOMEM;
+    if (precision != PIC_FP32 && precision != PIC_FP64) return PIC_EINVAL;
+    pic_batch* b = new (std::nothrow) pic_batch();
+    if (!b) return PIC_ENOMEM;
+    b->max_sims = max_sims;
+    b->dims = dims;
+    b->precision = precision;
+    b->table = reinterpret_cast<SimDev*>(dev_arena);
+    b->st = reinterpret_cast<hipStream_t>(hip_stream);
+    *out = b;
+    return PIC_OK;
+}
+
+static void batch_drop_graph(pic_batch* b)
+{
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+}
+
+extern "C" int pic_batch_add(pic_batch* b, pic_sim* s)
+{
+    if (!b || !s) return PIC_EINVAL;
+    if (!s->bound) return bfail(b, PIC_ESTATE, "simulation is not bound");
+    if (s->batch_refs) return bfail(b, PIC_ESTATE, "simulation already in a batch");
+    if ((int)b->members.size() >= b->max_sims) return bfail(b, PIC_ENOMEM, "batch is full");
+    if (s->g.dims != b->dims || s->g.precision != b->precision) return bfail(b, PIC_EINVAL, "dims or precision differ");
+    if (!b->st) return bfail(b, PIC_EINVAL, "a batch needs a non-default stream");
+    if (!b->members.empty() && s->g.sort_every != b->members[0]->g.sort_every)
+        return bfail(b, PIC_EINVAL, "members must share the sort period");
+    if (s->h.track) return bfail(b, PIC_EINVAL, "continuity tracking is not batched");
+    if (s->step % s->g.sort_every != 0) return bfail(b, PIC_ESTATE, "member must be at a multiple of its sort period");
+    if (s->st != b->st) return bfail(b, PIC_EINVAL, "member must be bound to the batch stream");
+    // first sort (bound species) outside the batch graph
+    if (s->need_sort || [&] { for (auto& x : s->sp) if (!x.sorted_once) return true; return false; }()) {
+        if (enqueue_sort_all(s, nullptr)) return bfail(b, PIC_EDEVICE, s->err.c_str());
+    }
+    s->batch_refs = 1;
+    s->d_batch = b->table + b->members.size();
+    b->members.push_back(s);
+    b->dirty = true;
+    return PIC_OK;
+}
+
+extern "C" int pic_batch_remove(pic_batch* b, pic_sim* s)
+{
+    if (!b || !s) return PIC_EINVAL;
+    auto it = std::find(b->members.begin(), b->members.end(), s);
+    if (it == b->members.end()) return bfail(b, PIC_EINVAL, "not a member");
+    if (hipStreamSynchronize(b->st) != hipSuccess) return bfail(b, PIC_EDEVICE, "sync failed");
+    b->members.erase(it);
+    s->batch_refs = 0;
+    s->d_batch = nullptr;
+    for (size_t i = 0; i < b->members.size(); ++i) b->members[i]->d_batch = b->table + i;
+    // bring the member's own table up to date with the batch copy (pointer parities)
+    upload_table(s);
+    b->dirty = true;
+    return PIC_OK;
+}
+
+extern "C" int pic_batch_size(const pic_batch* b) { return b ? (int)b->members.size() : 0; }
+
+extern "C" const char* pic_batch_last_error(const pic_batch* b) { return b ? b->err.c_str() : ""; }
+
+extern "C" void pic_batch_destroy(pic_batch* b)
+{
+    if (!b) return;
+    batch_drop_graph(b);
+    for (auto* s : b->members) s->batch_refs = 0;
+    delete b;
+}
+
+// one batched period: per-member sorts, then sort_every x (one particle launch + one field launch
+// over the whole batch)
+static int batch_enqueue_period(pic_batch* b, std::vector<std::vector<int>>* sorted)
+{
+    const int n = (int)b->members.size();
+    int max_vf = 1, max_vj = 1, lds = 1, pgrid = 1, ft = 0, block = 64;
+    for (int i = 0; i < n; ++i) {
+        pic_sim* s = b->members[i];
+        std::vector<int> mine;
+        // the member's sort kernels address the batch table entry
+        SimDev* keep = s->d;
+        s->d = b->table + i;
+        int r = enqueue_sort_all(s, &mine);
+        s->d = keep;
+        if (r) return bfail(b, r, s->err.c_str());
+        if (sorted) sorted->push_back(mine);
+        max_vf = std::max(max_vf, s->h.Vf);
+        max_vj = std::max(max_vj, s->h.Vj);
+        lds = std::max(lds, s->field_lds);
+        pgrid = std::max(pgrid, s->pgrid);
+        ft += s->h.nftiles;
+        block = std::max(block, s->g.block);
+    }
+    Launch L{};
+    L.sims = b->table;
+    L.nsims = n;
+    L.max_vf = max_vf;
+    L.max_vj = max_vj;
+    L.pgrid = pgrid;
+    L.block = block;
+    L.ftiles_total = ft;
+    L.stream = b->st;
+    const int P = b->members[0]->g.sort_every;
+    for (int k = 0; k < P; ++k) {
+        hipError_t e;
+        if (b->precision == PIC_FP32) {
+            e = Launchers<float>::particles(b->dims, L);
+            if (e == hipSuccess) e = Launchers<float>::fields(b->dims, L, lds);
+        } else {
+            e = Launchers<double>::particles(b->dims, L);
+            if (e == hipSuccess) e = Launchers<double>::fields(b->dims, L, lds);
+        }
+        if (e != hipSuccess) return bfail(b, PIC_EDEVICE, hipGetErrorString(e));
+    }
+    return PIC_OK;
+}
+
+extern "C" int pic_batch_step(pic_batch* b, int k)
+{
+    if (!b) return PIC_EINVAL;
+    if (b->members.empty()) return PIC_OK;
+    const int P = b->members[0]->g.sort_every;
+    if (k % P) return bfail(b, PIC_EINVAL, "k must be a multiple of the sort period");
+    if (b->dirty) {
+        // rewrite the device table with the members' current descriptors
+        batch_drop_graph(b);
+        for (size_t i = 0; i < b->members.size(); ++i) {
+            pic_sim* s = b->members[i];
+            for (size_t j = 0; j < s->sp.size(); ++j) mirror_species(s, (int)j);
+            if (hipMemcpyAsync(b->table + i, &s->h, sizeof(SimDev), hipMemcpyHostToDevice, b->st) != hipSuccess)
+                return bfail(b, PIC_EDEVICE, "table upload failed");
+        }
+        if (hipStreamSynchronize(b->st) != hipSuccess) return bfail(b, PIC_EDEVICE, "sync failed");
+        b->dirty = false;
+    }
+    for (int it = 0; it < k / P; ++it) {
+        if (!b->gexec) {
+            std::vector<std::vector<int>> sorted;
+            std::vector<std::vector<int>> par;
+            for (auto* s : b->members) {
+                std::vector<int> p;
+                for (auto& x : s->sp) p.push_back(x.parity);
+                par.push_back(p);
+            }
+            if (hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return bfail(b, PIC_EDEVICE, "capture failed");
+            int r = batch_enqueue_period(b, &sorted);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(b->st, &graph);
+            for (size_t i = 0; i < b->members.size(); ++i)
+                for (size_t j = 0; j < b->members[i]->sp.size(); ++j) b->members[i]->sp[j].parity = par[i][j];
+            if (r) { if (graph) (void)hipGraphDestroy(graph); return r; }
+            if (e != hipSuccess) return bfail(b, PIC_EDEVICE, hipGetErrorString(e));
+            e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) { b->gexec = nullptr; return bfail(b, PIC_EDEVICE, hipGetErrorString(e)); }
+            b->graph_k = 0;
+            // remember which species each member sorts inside the graph
+            for (size_t i = 0; i < b->members.size(); ++i) b->members[i]->graph_species = sorted[i];
+        }
+        if (hipGraphLaunch(b->gexec, b->st) != hipSuccess) return bfail(b, PIC_EDEVICE, "graph launch failed");
+        for (auto* s : b->members) {
+            for (int j : s->graph_species) s->sp[j].parity ^= 1;
+            s->step += P;
+        }
+    }
+    return PIC_OK;
+}

@@ -1,0 +1,169 @@
+// pic_internal.h -- device-resident descriptors of libpic (internal to the library).
+//
+// Every kernel reads its simulation from a SimDev table in device memory rather
+// than from kernel arguments, so a single simulation is a batch of one and the
+// batched form reuses the same kernels (membership changes rewrite the table;
+// captured graphs stay valid).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+constexpr int MAXSP = 4;
+constexpr int MAX_BATCH = 64;
+
+// Physical constants (CODATA 2018; e, c, hbar, kB exact).
+constexpr double kQe = 1.602176634e-19;
+constexpr double kMe = 9.1093837015e-31;
+constexpr double kC = 299792458.0;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kHbar = 1.054571817e-34;
+constexpr double kKb = 1.380649e-23;
+constexpr double kPi = 3.14159265358979323846;
+
+enum Kind { FREE = 0, BOUND = 1, DIRAC = 2 };
+enum Region { R_ALL = 0, R_BALL = 1, R_BOX = 2 };
+
+// Halo widths of the particle-tile windows (cells, per active axis).  A particle
+// may sit up to one cell outside its tile between sorts.  Gather reads nodes
+// c0-1..c0+1 of the start cell c0; the charge-conserving deposit writes nodes
+// c0-1..c0+2.  Hence the field window spans [lo-2, hi+2] and the current
+// window [lo-2, hi+3].
+constexpr int kGL = 2;       // low-side halo of both windows
+constexpr int kGHf = 2;      // high-side halo of the field window
+constexpr int kGHj = 3;      // high-side halo of the current window
+
+struct SpeciesDev {
+    int kind, reflect, region, sheet_normal;
+    int n;                 // particle count
+    int sortable;          // 0 for bound species after their first sort (anchors never move)
+    double qm;             // q / m
+    double qw;             // q * weight
+    double mw;             // m * weight
+    double w2[3], gam[3];  // bound: omega_b^2, gamma_b
+    double bw;             // bound: weight of the magnetic force
+    double vf;             // Dirac: Fermi speed
+    double rc[3], rr, rlo[3], rhi[3];  // region (cell units)
+    // state, structure of arrays; R = float or double by precision
+    int* cell;             // packed cell index (free/Dirac: current cell; bound: anchor cell)
+    void* off[3];          // in-cell offset in [0,1) (bound: anchor offset)
+    void* v[3];            // velocity v_{n-1/2} [m/s]
+    void* xi[3];           // bound: displacement from the anchor [m]
+    // second copy for the sort permutation (pointers swapped after each sort)
+    int* cell_alt;
+    void* off_alt[3];
+    void* v_alt[3];
+    void* xi_alt[3];
+    int* tile_start;       // [ntiles + 1] first particle of each tile
+    // sort scratch
+    int* keys;
+    int* keys_alt;
+    int* vals;
+    int* vals_alt;
+};
+
+struct SimDev {
+    int dims, precision, nspecies, ntiles;
+    int n[3], L[3], periodic[3], T[3], Tshift[3], ntile[3];
+    int Wf[3], Wj[3];      // particle-window extents (1 on inactive axes)
+    int gl[3];             // low halo per axis (kGL on active axes, 0 otherwise)
+    int Vf, Vj;            // window volumes
+    int pshift[3], pmask[3];  // packed cell: c = (cell >> pshift) & pmask
+    int FT[3], nft[3], nftiles;  // field tiles
+    long long Lvol;
+    double dx[3], inv_dx[3], dt_dx[3], dt;
+    double mur_k[3];       // (c dt - dx) / (c dt + dx)
+    // fields, planar [comp][z][y][x], R
+    void* E[3];
+    void* B[3];
+    void* slots;           // per active tile: [3][Vj] current window
+    int* tile_slot;        // [ntiles]: slot of an active tile, -1 otherwise
+    int* active;           // [ntiles]: active tile list
+    int* n_active;         // device scalar
+    int max_slots;         // capacity of the slot array (tiles that can hold particles)
+    int* sort_hist;        // radix-sort digit histogram scratch
+    void* jover[2];        // [3][Lvol] current of particles outside their window (rare)
+    long long* over_stamp; // [2] step+1 of the last overflow per parity
+    unsigned long long* over_count;
+    double* partials;      // [ntiles][3] per active tile: sum q w v_{n+1/2}
+    double* series;        // [series_cap][3]
+    int series_cap;
+    long long* step_p;     // steps pushed (written by the particle kernel)
+    long long* step_f;     // steps whose fields are done (written by the field kernel)
+    // source
+    int src_kind, src_comp, src_axis, src_index[3];
+    double src_j0, src_omega, src_tau;
+    // diagnostics
+    int track;             // keep the merged particle current of the last step
+    void* jtrack;          // [3][Lvol] R
+    double* rho_ion;       // [Lvol]
+    double* rho_a;         // [Lvol]
+    double* rho_b;         // [Lvol]
+    double* red;           // reduction scratch
+    SpeciesDev sp[MAXSP];
+};
+
+// ---- small host/device helpers ----------------------------------------------------------------
+__host__ __device__ inline int pack_cell(const SimDev& S, int i, int j, int k)
+{
+    return (i << S.pshift[0]) | (j << S.pshift[1]) | (k << S.pshift[2]);
+}
+
+__host__ __device__ inline void unpack_cell(const SimDev& S, int c, int out[3])
+{
+    out[0] = (c >> S.pshift[0]) & S.pmask[0];
+    out[1] = (c >> S.pshift[1]) & S.pmask[1];
+    out[2] = (c >> S.pshift[2]) & S.pmask[2];
+}
+
+// Tile-major cell key: tile id, then the cell inside the tile (x fastest).
+__host__ __device__ inline int cell_key(const SimDev& S, const int c[3])
+{
+    int tid = ((c[2] >> S.Tshift[2]) * S.ntile[1] + (c[1] >> S.Tshift[1])) * S.ntile[0] + (c[0] >> S.Tshift[0]);
+    int loc = (((c[2] & (S.T[2] - 1)) << S.Tshift[1]) + (c[1] & (S.T[1] - 1))) << S.Tshift[0];
+    loc += c[0] & (S.T[0] - 1);
+    return (tid << (S.Tshift[0] + S.Tshift[1] + S.Tshift[2])) + loc;
+}
+
+// ---- launchers (defined in the kernel translation units) ---------------------------------------
+struct Launch {
+    const SimDev* sims;    // device table
+    int nsims;
+    int max_vf, max_vj;    // LDS sizing over members
+    int pgrid;             // particle-kernel grid
+    int block;             // particle-kernel block
+    int ftiles_total;      // field tiles over members
+    hipStream_t stream;
+};
+
+struct LoadArgs {
+    int s, sid, ppc, ncell, momentum, loading, pert_mode, ntab;
+    unsigned long long seed;
+    double e_fermi, kT, mass, pert_amp, xi_radius, e_max;
+    const int* cells;     // packed region cells, row-major order
+    const double* cdf;    // FD CDF on x = sqrt(e / e_max), ntab + 1 nodes
+};
+
+// Launchers of the precision-templated kernels; explicitly instantiated for float (pic_k32.hip)
+// and double (pic_k64.hip).
+template <typename R>
+struct Launchers {
+    static hipError_t particles(int dims, const Launch& L);
+    static hipError_t fields(int dims, const Launch& L, int lds_elems);
+    static hipError_t load(int dims, SimDev* dS, const LoadArgs& A, hipStream_t st);
+    static hipError_t field_energy(const SimDev* dS, double* part, int nb, hipStream_t st);
+    static hipError_t kinetic(const SimDev* dS, int s, double* part, int nb, hipStream_t st);
+    static hipError_t rho(int dims, const SimDev* dS, double* rho, int nb, hipStream_t st);
+    static hipError_t gauss(int dims, const SimDev* dS, const double* rho, double* part, int nb, hipStream_t st);
+    static hipError_t continuity(int dims, const SimDev* dS, double* part, int nb, hipStream_t st);
+    static hipError_t gauss_init_1d(const SimDev* dS, const double* rho, hipStream_t st);
+};
+
+// Untyped helpers (pic_sort.hip).
+hipError_t enqueue_fill(void* p, size_t bytes, hipStream_t st);  // zero fill by kernel (graph safe)
+hipError_t enqueue_sum(const double* x, long long n, double* part, int nb, hipStream_t st);
+hipError_t enqueue_final(const double* part, int nb, int nv, int op, double* out, hipStream_t st);
+hipError_t enqueue_ion(SimDev* dS, const double* rho, int uniform, const double* total, hipStream_t st);
+
+}  // namespace pic

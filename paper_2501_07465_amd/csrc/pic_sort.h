@@ -1,0 +1,19 @@
+// pic_sort.h -- enqueue functions of the cell sort (pic_sort.hip).
+#pragma once
+#include "pic_internal.h"
+
+namespace pic {
+
+constexpr int kSortIpb = 4096;  // keys per radix-sort block
+
+// Stable radix sort of species s by cell key (passes of 8 bits), permutation of its arrays
+// into the alternates and pointer swap.  elem = 4 (FP32 form) or 8 (FP64 form).
+hipError_t enqueue_sort(SimDev* dS, int s, int n, int passes, int elem, hipStream_t st);
+// Per-tile particle ranges of species s from its sorted keys.
+hipError_t enqueue_ranges(SimDev* dS, int s, int ntiles, int passes, hipStream_t st);
+// Keys of species s into its key buffer (diagnostics).
+hipError_t enqueue_keys_only(SimDev* dS, int s, int n, hipStream_t st);
+// Active tile list and slots.
+hipError_t enqueue_compact(SimDev* dS, hipStream_t st);
+
+}  // namespace pic

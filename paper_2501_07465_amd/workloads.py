@@ -114,7 +114,7 @@ def disk2d(n=1024, radius=100.0, ppc_free=16, ppc_bound=16, steps=4000, tile=(16
             "ion": "local", "steps": steps, "seed": 2, "precision": "fp32"}
 
 
-def sphere3d(n=256, radius=100.0, ppc_free=8, ppc_bound=8, steps=2000, tile=(8, 8, 8), src_gap=14):
+def sphere3d(n=256, radius=100.0, ppc_free=8, ppc_bound=8, steps=2000, tile=(8, 8, 4), src_gap=14):
     dx = 1e-9
     c = n / 2.0
     ball = {"kind": "ball", "center": [c, c, c], "radius": radius}
