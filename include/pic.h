@@ -198,6 +198,13 @@ enum {
 };
 int pic_diag(pic_sim* s, int kind, int arg, double* out, size_t cap, size_t* n_out);
 
+/* Run nsteps plain (non-graph) steps with HIP events recorded on the bound
+ * stream around each launch and return average device times in milliseconds:
+ * out[0] particle kernel, out[1] field kernel, out[2] one cell sort of all
+ * species (0 if none ran), out[3] number of sorts timed.  Synchronises.
+ * Errors: PIC_ESTATE, PIC_EDEVICE. */
+int pic_time_kernels(pic_sim* s, int nsteps, double out[4]);
+
 /* Wait for all enqueued work.  Errors: PIC_EDEVICE. */
 int pic_sync(pic_sim* s);
 

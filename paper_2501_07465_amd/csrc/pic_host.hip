@@ -466,8 +466,10 @@ static size_t plan(pic_sim* s, char* base, bool assign)
     const size_t es = s->es;
     const size_t L = (size_t)h.Lvol;
     s->d = P.take<SimDev>(1);
-    for (int c = 0; c < 3; ++c) h.E[c] = P.takeb(L * es);
-    for (int c = 0; c < 3; ++c) h.B[c] = P.takeb(L * es);
+    for (int k = 0; k < 2; ++k) {
+        for (int c = 0; c < 3; ++c) h.E[k][c] = P.takeb(L * es);
+        for (int c = 0; c < 3; ++c) h.B[k][c] = P.takeb(L * es);
+    }
     for (int p = 0; p < 2; ++p) h.jover[p] = P.takeb(3 * L * es);
     s->max_slots = count_slot_tiles(s);
     h.max_slots = s->max_slots;
@@ -725,7 +727,8 @@ extern "C" int pic_load_fields(pic_sim* s, const double* e, const double* b)
             const double* src = w == 0 ? e : b;
             if (!src) continue;
             if (s->es == 4) to_real<float>(src + c * L, L, buf); else to_real<double>(src + c * L, L, buf);
-            HIPCHK(s, hipMemcpyAsync(w == 0 ? s->h.E[c] : s->h.B[c], buf.data(), buf.size(), hipMemcpyHostToDevice, s->st));
+            const int par = (int)(s->step & 1);
+            HIPCHK(s, hipMemcpyAsync(w == 0 ? s->h.E[par][c] : s->h.B[par][c], buf.data(), buf.size(), hipMemcpyHostToDevice, s->st));
             HIPCHK(s, hipStreamSynchronize(s->st));
         }
     }
@@ -756,8 +759,9 @@ extern "C" int pic_init_fields(pic_sim* s, int mode)
         HIPCHK(s, enqueue_ion(s->d, s->h.rho_a, 1, s->outv, s->st));
     }
     if (mode == 2) {
-        if (s->g.precision == PIC_FP32) HIPCHK(s, Launchers<float>::gauss_init_1d(s->d, s->h.rho_a, s->st));
-        else HIPCHK(s, Launchers<double>::gauss_init_1d(s->d, s->h.rho_a, s->st));
+        const int par = (int)(s->step & 1);
+        if (s->g.precision == PIC_FP32) HIPCHK(s, Launchers<float>::gauss_init_1d(s->d, par, s->h.rho_a, s->st));
+        else HIPCHK(s, Launchers<double>::gauss_init_1d(s->d, par, s->h.rho_a, s->st));
     }
     HIPCHK(s, hipStreamSynchronize(s->st));
     return PIC_OK;
@@ -897,6 +901,53 @@ extern "C" int pic_step(pic_sim* s, int nsteps)
     return PIC_OK;
 }
 
+extern "C" int pic_time_kernels(pic_sim* s, int nsteps, double out[4])
+{
+    if (!s || !out) return PIC_EINVAL;
+    if (!s->bound) return fail(s, PIC_ESTATE, "bind first");
+    if (s->batch_refs) return fail(s, PIC_ESTATE, "simulation is in a batch");
+    hipEvent_t ev[6];
+    for (auto& e : ev) HIPCHK(s, hipEventCreate(&e));
+    double tp = 0.0, tf = 0.0, ts = 0.0;
+    int nsort = 0, r = PIC_OK;
+    for (int k = 0; k < nsteps && !r; ++k) {
+        const bool sort = s->need_sort || s->step % s->g.sort_every == 0;
+        if (sort) {
+            if ((r = (hipEventRecord(ev[4], s->st) == hipSuccess ? PIC_OK : PIC_EDEVICE))) break;
+            if ((r = enqueue_sort_all(s, nullptr))) break;
+            if ((r = (hipEventRecord(ev[5], s->st) == hipSuccess ? PIC_OK : PIC_EDEVICE))) break;
+        }
+        const Launch L = make_launch(s);
+        hipError_t e = hipEventRecord(ev[0], s->st);
+        if (e == hipSuccess) e = s->g.precision == PIC_FP32 ? Launchers<float>::particles(s->g.dims, L)
+                                                            : Launchers<double>::particles(s->g.dims, L);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], s->st);
+        if (e == hipSuccess) e = s->g.precision == PIC_FP32 ? Launchers<float>::fields(s->g.dims, L, s->field_lds)
+                                                            : Launchers<double>::fields(s->g.dims, L, s->field_lds);
+        if (e == hipSuccess) e = hipEventRecord(ev[2], s->st);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
+        if (e != hipSuccess) { r = fail(s, PIC_EDEVICE, "timing: %s", hipGetErrorString(e)); break; }
+        float a = 0.f, b = 0.f, c = 0.f;
+        (void)hipEventElapsedTime(&a, ev[0], ev[1]);
+        (void)hipEventElapsedTime(&b, ev[1], ev[2]);
+        tp += a;
+        tf += b;
+        if (sort) {
+            (void)hipEventElapsedTime(&c, ev[4], ev[5]);
+            ts += c;
+            ++nsort;
+        }
+        s->step++;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (r) return r;
+    out[0] = nsteps > 0 ? tp / nsteps : 0.0;
+    out[1] = nsteps > 0 ? tf / nsteps : 0.0;
+    out[2] = nsort > 0 ? ts / nsort : 0.0;
+    out[3] = (double)nsort;
+    return PIC_OK;
+}
+
 extern "C" int pic_sync(pic_sim* s)
 {
     if (!s) return PIC_EINVAL;
@@ -941,6 +992,7 @@ extern "C" int pic_diag(pic_sim* s, int kind, int arg, double* out, size_t cap, 
     const bool f32 = s->g.precision == PIC_FP32;
     const size_t L = (size_t)s->h.Lvol;
     const int nsp = (int)s->sp.size();
+    const int par = (int)(s->step & 1);  // field buffer holding the current E, B
     size_t need = 0;
     switch (kind) {
     case PIC_DIAG_FIELD_ENERGY: case PIC_DIAG_STEP: case PIC_DIAG_OVERFLOW: need = 1; break;
@@ -963,8 +1015,8 @@ extern "C" int pic_diag(pic_sim* s, int kind, int arg, double* out, size_t cap, 
     if (!out || cap < need) return fail(s, PIC_ETRUNC, "output needs %zu values", need);
     switch (kind) {
     case PIC_DIAG_FIELD_ENERGY: {
-        if (f32) HIPCHK(s, Launchers<float>::field_energy(dtab(s), s->part, kDiagBlocks, s->st));
-        else HIPCHK(s, Launchers<double>::field_energy(dtab(s), s->part, kDiagBlocks, s->st));
+        if (f32) HIPCHK(s, Launchers<float>::field_energy(dtab(s), par, s->part, kDiagBlocks, s->st));
+        else HIPCHK(s, Launchers<double>::field_energy(dtab(s), par, s->part, kDiagBlocks, s->st));
         HIPCHK(s, enqueue_final(s->part, kDiagBlocks, 1, 0, s->outv, s->st));
         int r = fetch_doubles(s, s->outv, 1, out);
         if (r) return r;
@@ -985,8 +1037,8 @@ extern "C" int pic_diag(pic_sim* s, int kind, int arg, double* out, size_t cap, 
     }
     case PIC_DIAG_GAUSS_RESIDUAL: {
         HIPCHK(s, launch_rho(s, s->h.rho_b));
-        if (f32) HIPCHK(s, Launchers<float>::gauss(s->g.dims, dtab(s), s->h.rho_b, s->part, kDiagBlocks, s->st));
-        else HIPCHK(s, Launchers<double>::gauss(s->g.dims, dtab(s), s->h.rho_b, s->part, kDiagBlocks, s->st));
+        if (f32) HIPCHK(s, Launchers<float>::gauss(s->g.dims, dtab(s), par, s->h.rho_b, s->part, kDiagBlocks, s->st));
+        else HIPCHK(s, Launchers<double>::gauss(s->g.dims, dtab(s), par, s->h.rho_b, s->part, kDiagBlocks, s->st));
         HIPCHK(s, enqueue_final(s->part, kDiagBlocks, 2, 1, s->outv, s->st));
         return fetch_doubles(s, s->outv, 2, out);
     }
@@ -1033,8 +1085,8 @@ extern "C" int pic_diag(pic_sim* s, int kind, int arg, double* out, size_t cap, 
     case PIC_DIAG_EXPORT_FIELDS: {
         int r;
         for (int c = 0; c < 3; ++c) {
-            if ((r = fetch_real(s, s->h.E[c], L, out + c * L, 1))) return r;
-            if ((r = fetch_real(s, s->h.B[c], L, out + (3 + c) * L, 1))) return r;
+            if ((r = fetch_real(s, s->h.E[par][c], L, out + c * L, 1))) return r;
+            if ((r = fetch_real(s, s->h.B[par][c], L, out + (3 + c) * L, 1))) return r;
         }
         return PIC_OK;
     }

@@ -74,9 +74,9 @@ struct SimDev {
     long long Lvol;
     double dx[3], inv_dx[3], dt_dx[3], dt;
     double mur_k[3];       // (c dt - dx) / (c dt + dx)
-    // fields, planar [comp][z][y][x], R
-    void* E[3];
-    void* B[3];
+    // fields, planar [comp][z][y][x], R; two buffers: step n reads [n & 1] and writes [(n+1) & 1]
+    void* E[2][3];
+    void* B[2][3];
     void* slots;           // per active tile: [3][Vj] current window
     int* tile_slot;        // [ntiles]: slot of an active tile, -1 otherwise
     int* active;           // [ntiles]: active tile list
@@ -152,12 +152,12 @@ struct Launchers {
     static hipError_t particles(int dims, const Launch& L);
     static hipError_t fields(int dims, const Launch& L, int lds_elems);
     static hipError_t load(int dims, SimDev* dS, const LoadArgs& A, hipStream_t st);
-    static hipError_t field_energy(const SimDev* dS, double* part, int nb, hipStream_t st);
+    static hipError_t field_energy(const SimDev* dS, int par, double* part, int nb, hipStream_t st);
     static hipError_t kinetic(const SimDev* dS, int s, double* part, int nb, hipStream_t st);
     static hipError_t rho(int dims, const SimDev* dS, double* rho, int nb, hipStream_t st);
-    static hipError_t gauss(int dims, const SimDev* dS, const double* rho, double* part, int nb, hipStream_t st);
+    static hipError_t gauss(int dims, const SimDev* dS, int par, const double* rho, double* part, int nb, hipStream_t st);
     static hipError_t continuity(int dims, const SimDev* dS, double* part, int nb, hipStream_t st);
-    static hipError_t gauss_init_1d(const SimDev* dS, const double* rho, hipStream_t st);
+    static hipError_t gauss_init_1d(const SimDev* dS, int par, const double* rho, hipStream_t st);
 };
 
 // Untyped helpers (pic_sort.hip).

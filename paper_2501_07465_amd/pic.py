@@ -34,7 +34,7 @@ PIC_SRC_NONE, PIC_SRC_SHEET, PIC_SRC_POINT = 0, 1, 2
 
 EXPORTED = ["pic_create", "pic_init_species", "pic_footprint", "pic_bind", "pic_load_particles",
             "pic_load_fields", "pic_field_shape", "pic_init_fields", "pic_step", "pic_use_graphs",
-            "pic_diag", "pic_sync", "pic_species_count", "pic_last_error", "pic_destroy",
+            "pic_diag", "pic_time_kernels", "pic_sync", "pic_species_count", "pic_last_error", "pic_destroy",
             "pic_batch_footprint", "pic_batch_create", "pic_batch_add", "pic_batch_remove",
             "pic_batch_step", "pic_batch_size", "pic_batch_last_error", "pic_batch_destroy"]
 
@@ -88,6 +88,7 @@ def lib():
         L.pic_use_graphs.argtypes = [_VP, C.c_int]
         L.pic_diag.argtypes = [_VP, C.c_int, C.c_int, _D, C.c_size_t, C.POINTER(C.c_size_t)]
         L.pic_sync.argtypes = [_VP]
+        L.pic_time_kernels.argtypes = [_VP, C.c_int, _D]
         L.pic_species_count.argtypes = [_VP, C.c_int]
         L.pic_species_count.restype = C.c_longlong
         L.pic_last_error.argtypes = [_VP]
@@ -186,6 +187,13 @@ def pic_diag(h, kind: int, arg: int = -1) -> np.ndarray:
     out = np.zeros(max(n.value, 1))
     _check(lib().pic_diag(h, kind, arg, out.ctypes.data_as(_D), out.size, C.byref(n)), h)
     return out[:n.value]
+
+
+def pic_time_kernels(h, nsteps: int):
+    """Average device ms per launch: particle kernel, field kernel, one sort, number of sorts."""
+    out = np.zeros(4)
+    _check(lib().pic_time_kernels(h, nsteps, out.ctypes.data_as(_D)), h)
+    return out
 
 
 def pic_sync(h):
