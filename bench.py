@@ -71,10 +71,11 @@ def occupied_cells(sim_counts, w):
     return int(cells.sum())
 
 
-def run_gpu(w, precision, steps, warmup, graphs=True, time_kernels=0):
+def run_gpu(w, precision, steps, warmup, graphs=True, time_kernels=0, block=256):
     import torch
     from paper_2501_07465_amd import pic
-    sim = pic.Simulation(w, precision=precision, graphs=graphs, series_cap=steps + warmup + time_kernels + 64)
+    sim = pic.Simulation(w, precision=precision, graphs=graphs, series_cap=steps + warmup + time_kernels + 64,
+                         block=block)
     counts = [sim.count(s) for s in sim.species]
     sim.step(warmup)
     sim.sync()
@@ -120,6 +121,10 @@ def main():
     ap.add_argument("--time-kernels", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tile", type=str, default=None, help="particle tile, e.g. 8x8")
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -128,9 +133,19 @@ def main():
     from paper_2501_07465_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     w = W.WORKLOADS[args.workload]()
+    if args.tile:
+        t = [int(v) for v in args.tile.split("x")]
+        w["tile"] = t + [1] * (3 - len(t))
     graphs = not args.no_graphs
+    if args.copy_mib:
+        src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(f"bench: {args.workload} fp32 warmup {args.warmup} steps {args.steps}", file=sys.stderr, flush=True)
-    sim, counts, dt32, kt, fe = run_gpu(w, "fp32", args.steps, args.warmup, graphs, args.time_kernels)
+    sim, counts, dt32, kt, fe = run_gpu(w, "fp32", args.steps, args.warmup, graphs, args.time_kernels, args.block)
     npart = sum(counts)
     rate32 = npart * args.steps / dt32
     del sim
@@ -158,7 +173,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w['name']}: 2D3V {w['n'][0]}x{w['n'][1]} cells of 1 nm, disk radius 100 cells, "
                                f"16 ppc FD free + 16 ppc bound ({npart} particles), 800 nm pulse, FP32",
-                   "particles": npart, "graphs": graphs},
+                   "particles": npart, "graphs": graphs, "tile": w["tile"], "block": args.block},
         "fp64": {"value": rate64, "unit": "particle-steps/s", "steps": args.fp64_steps,
                  "ms_per_step": dt64 / args.fp64_steps * 1e3, "fp32_speedup": rate32 / rate64},
         "kernels_ms": {"particles": t_particle_ms, "fields": float(kt[1]), "sort": float(kt[2])},

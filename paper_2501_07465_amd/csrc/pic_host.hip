@@ -202,7 +202,9 @@ static int setup_grid(pic_sim* s)
     const size_t plds = (size_t)s->es * (6 * (size_t)h.Vf + 3 * (size_t)h.Vj);
     if (plds > 65536) return fail(s, PIC_EINVAL, "particle tile needs %zu bytes of LDS (> 64 KiB)", plds);
     // field tiles
-    const int ft[3][3] = {{256, 1, 1}, {32, 8, 1}, {16, 4, 4}};
+    const int ft[3][3] = {{FieldTile<1>::X, FieldTile<1>::Y, FieldTile<1>::Z},
+                          {FieldTile<2>::X, FieldTile<2>::Y, FieldTile<2>::Z},
+                          {FieldTile<3>::X, FieldTile<3>::Y, FieldTile<3>::Z}};
     h.Lvol = 1;
     h.nftiles = 1;
     for (int a = 0; a < 3; ++a) {

@@ -30,6 +30,16 @@ enum Region { R_ALL = 0, R_BALL = 1, R_BOX = 2 };
 // c0-1..c0+1 of the start cell c0; the charge-conserving deposit writes nodes
 // c0-1..c0+2.  Hence the field window spans [lo-2, hi+2] and the current
 // window [lo-2, hi+3].
+// Field-kernel tile (cells) per number of active axes: x, y, z.
+template <int DIM>
+struct FieldTile;
+template <>
+struct FieldTile<1> { static constexpr int X = 256, Y = 1, Z = 1; };
+template <>
+struct FieldTile<2> { static constexpr int X = 32, Y = 8, Z = 1; };
+template <>
+struct FieldTile<3> { static constexpr int X = 16, Y = 4, Z = 4; };
+
 constexpr int kGL = 2;       // low-side halo of both windows
 constexpr int kGHf = 2;      // high-side halo of the field window
 constexpr int kGHj = 3;      // high-side halo of the current window
