@@ -413,3 +413,57 @@ class Simulation:
     @property
     def steps_done(self):
         return int(pic_diag(self.h, DIAG_STEP)[0])
+
+
+class Batch:
+    """Several simulations of the same dimensionality and precision stepped by one persistent particle
+    launch and one field launch per step (one captured graph per sort period).  Members must be
+    bound to the batch's stream."""
+
+    def __init__(self, max_sims: int, dims: int, precision: str = "fp32", stream=None):
+        import torch
+        self.b = None
+        self.max_sims = max_sims
+        self.dims = dims
+        self.precision = precision
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        nb = pic_batch_footprint(max_sims, dims)
+        self.table = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        self.b = pic_batch_create(max_sims, dims, PIC_FP64 if precision == "fp64" else PIC_FP32,
+                                  self.table.data_ptr(), nb, self.stream.cuda_stream)
+        self.members = []
+
+    def add(self, sim: "Simulation"):
+        pic_batch_add(self.b, sim.h)
+        self.members.append(sim)
+
+    def remove(self, sim: "Simulation"):
+        pic_batch_remove(self.b, sim.h)
+        self.members.remove(sim)
+
+    def step(self, k: int):
+        pic_batch_step(self.b, k)
+
+    def __len__(self):
+        return pic_batch_size(self.b)
+
+    def __del__(self):
+        if getattr(self, "b", None):
+            for s in list(getattr(self, "members", [])):
+                try:
+                    pic_batch_remove(self.b, s.h)
+                except Exception:
+                    pass
+            pic_batch_destroy(self.b)
+            self.b = None
+
+
+def footprint_of(w: dict, precision: str | None = None, block: int = 256, series_cap: int | None = None) -> int:
+    """Device bytes a simulation of workload ``w`` needs (host-only planning, nothing allocated)."""
+    h = pic_create(grid_desc(w, precision, False, block, series_cap))
+    try:
+        for sp in w["species"]:
+            pic_init_species(h, species_desc(sp), w.get("seed", 1))
+        return pic_footprint(h)
+    finally:
+        pic_destroy(h)

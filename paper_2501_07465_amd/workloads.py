@@ -145,7 +145,7 @@ def stream_request(j: int, rng_seed_base: int = 1000, scale: float = 1.0):
 
     Grid side uniform in [128, 1024] cells (times ``scale``); disk, rod or slab
     geometry with seeded dimensions; 8-32 ppc free FD electrons plus 8-32 ppc bound
-    electrons; 500-4000 steps.
+    electrons; 500-4000 steps (a multiple of the 20-step sort period).
     """
     rng = np.random.default_rng(rng_seed_base + j)
     n = int(rng.integers(128, 1025))
@@ -153,7 +153,7 @@ def stream_request(j: int, rng_seed_base: int = 1000, scale: float = 1.0):
     geom = ["disk", "rod", "slab"][int(rng.integers(0, 3))]
     ppc_f = int(rng.integers(8, 33))
     ppc_b = int(rng.integers(8, 33))
-    steps = int(rng.integers(500, 4001))
+    steps = 20 * int(rng.integers(25, 201))  # 500..4000, a whole number of sort periods
     c = n / 2.0
     if geom == "disk":
         d = float(rng.uniform(0.2, 0.6)) * n

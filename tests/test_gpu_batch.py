@@ -1,0 +1,130 @@
+"""Batched and served simulations give the same results as the same simulations run alone.
+
+FP64 batch: element by element within 1e-12 of the same simulations stepped alone (and of the
+oracle).  FP32 batch and serving mix: end-of-run field energy, kinetic energies and the spectrum
+of the total-current series within 1e-3 relative of the run alone.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b, scale=None):
+    scale = np.max(np.abs(b)) if scale is None else scale
+    return float(np.max(np.abs(a - b)) / max(scale, 1e-300)) if np.size(a) else 0.0
+
+
+def _uneven(n_req=3, steps=40):
+    """Small uneven 2D requests: different grids, geometries, ppc."""
+    from paper_2501_07465_amd import workloads as W
+    out = []
+    for j in range(n_req):
+        w = W.stream_request(j, scale=0.1)
+        w["steps"] = steps
+        w["tile"] = [16, 8, 1]
+        out.append(w)
+    return out
+
+
+def _spectrum(series):
+    s = np.asarray(series)
+    win = np.hanning(s.shape[0])[:, None]
+    return np.abs(np.fft.rfft(s * win, axis=0))
+
+
+def _compare_results(a, b, tol, label):
+    ef = abs(a["field_energy"] - b["field_energy"]) / max(abs(b["field_energy"]), 1e-300)
+    ek = max(abs(x - y) / max(abs(y), 1e-300) for x, y in zip(a["kinetic_energy"], b["kinetic_energy"]))
+    sa, sb = _spectrum(a["current_series"]), _spectrum(b["current_series"])
+    es = _rel(sa, sb)
+    print(f"{label}: field energy {ef:.2e}, kinetic {ek:.2e}, current spectrum {es:.2e}", flush=True)
+    assert a["steps"] == b["steps"]
+    assert ef <= tol and ek <= tol and es <= tol, (label, ef, ek, es)
+
+
+def test_batch_fp64_matches_alone_and_oracle(oracle):
+    from paper_2501_07465_amd import pic
+    ws = _uneven(3, 40)
+    print("case batch fp64: " + ", ".join(f"{w['n'][0]}^2 {w['geometry']}" for w in ws), flush=True)
+    alone = []
+    for w in ws:
+        s = pic.Simulation(w, precision="fp64", graphs=False)
+        s.step(40)
+        alone.append(s)
+    batch = pic.Batch(4, 2, "fp64")
+    mixed = [pic.Simulation(w, precision="fp64", graphs=False, stream=batch.stream) for w in ws]
+    for s in mixed:
+        batch.add(s)
+    batch.step(20)
+    batch.step(20)
+    for s in list(mixed):
+        batch.remove(s)
+    for i, (a, m) in enumerate(zip(alone, mixed)):
+        assert m.steps_done == 40
+        for sid in range(len(ws[i]["species"])):
+            xa, va, _ = a.particles(sid)
+            xm, vm, _ = m.particles(sid)
+            assert _rel(xm, xa) < 1e-12 and _rel(vm, va) < 1e-12, (i, sid)
+        ea, ba = a.fields()
+        em, bm = m.fields()
+        assert _rel(em, ea) < 1e-12 and _rel(bm, ba, np.max(np.abs(ea)) / 3e8 + np.max(np.abs(ba))) < 1e-12, i
+    # one member against the oracle from the same initial state
+    ref = oracle.build_workload(ws[0])
+    s = pic.Simulation(ws[0], precision="fp64", states=ref.state(), fields=ref.fields(), graphs=False,
+                       stream=batch.stream)
+    batch.add(s)
+    batch.step(40)
+    batch.remove(s)
+    ref.step(40)
+    eg, _ = s.fields()
+    er, _ = ref.fields()
+    print(f"batch fp64 vs oracle: E rel {_rel(eg, er):.2e}", flush=True)
+    assert _rel(eg, er) < 1e-12
+
+
+def test_batch_fp32_member_joining_mid_run():
+    from paper_2501_07465_amd import pic, serve
+    ws = _uneven(3, 80)
+    print("case batch fp32 join", flush=True)
+    ref = [serve.run_alone(w, "fp32") for w in ws]
+    batch = pic.Batch(4, 2, "fp32")
+    sims = [pic.Simulation(w, precision="fp32", graphs=False, stream=batch.stream, block=512,
+                           series_cap=w["steps"] + 64) for w in ws]
+    batch.add(sims[0])
+    batch.add(sims[1])
+    batch.step(40)
+    batch.add(sims[2])  # joins while the others are mid-run
+    batch.step(40)
+    batch.remove(sims[0])
+    batch.remove(sims[1])
+    batch.step(40)
+    batch.remove(sims[2])
+    for i, s in enumerate(sims):
+        res = {"field_energy": s.field_energy(), "kinetic_energy": [s.kinetic_energy(k) for k in s.species],
+               "current_series": s.current_series(), "steps": s.steps_done}
+        _compare_results(res, ref[i], 1e-3, f"batch fp32 member {i}")
+
+
+def test_serving_results_same_alone_and_in_mix():
+    from paper_2501_07465_amd import serve, workloads as W
+    reqs = []
+    for j in range(5):
+        w = W.stream_request(j, scale=0.1)
+        w["steps"] = 40 * (1 + j % 3)
+        w["tile"] = [16, 8, 1]
+        reqs.append(serve.Request(j, w, arrival=0.02 * j))
+    print("case serving mix", flush=True)
+    ref = [serve.run_alone(r.w, "fp32") for r in reqs]
+    # a budget that holds about three of them at once: later arrivals wait for memory
+    fps = []
+    for r in reqs:
+        from paper_2501_07465_amd import pic
+        fps.append(pic.footprint_of(r.w, "fp32", 512, series_cap=r.steps + 64))
+    srv = serve.Server(dims=2, precision="fp32", hbm_budget=int(sum(sorted(fps)[-3:])), max_slots=4)
+    stats = srv.run(reqs)
+    print(f"serving: {stats}", flush=True)
+    assert stats["requests"] == len(reqs) and stats["rejected"] == 0
+    assert stats["p99_s"] >= stats["p50_s"] > 0
+    for r, a in zip(reqs, ref):
+        _compare_results(r.result, a, 1e-3, f"request {r.rid}")
