@@ -1,23 +1,32 @@
-"""Benchmark of the PIC step on one MI355X: particle-steps/s (gather + push + deposit + fields).
+"""Benchmark of the PIC step on one MI355X: particle-steps/s (sort + gather + push + deposit + fields).
 
-Workload: the 2D3V disk (1024 x 1024 cells of 1 nm, 200 nm metal disk, 16 ppc Fermi-Dirac
-free electrons + 16 ppc bound Lorentz electrons, 800 nm plane-wave pulse), FP32 form, with
-synthetic seeded inputs.  W warm-up steps, then exactly K timed steps (HIP graphs replay one
-sort period of steps at a time), bracketed by device synchronisation.  The FP64 GPU rate of the
-same workload is reported beside it, as is the plain-C FP64 oracle timed on the host on a
-bounded sample (cpu_baseline).
+Default workload: the 2D3V disk (1024 x 1024 cells of 1 nm, 200 nm metal disk, 16 ppc Fermi-Dirac
+free electrons + 16 ppc bound Lorentz electrons, 800 nm pulse at 1e9 V/m), FP32 form (int32 cell +
+FP32 offset), synthetic seeded inputs.  W warm-up steps, then exactly K timed steps (captured
+graphs replay one 20-step sort period at a time), bracketed by device synchronisation.
 
-roofline: the dominant kernel is the particle-tile kernel.  Its algorithmic bytes per launch are
-the particle state read and written (per particle: 2D free 48 B, 2D bound 60 B, Dirac 48 B in
-FP32) plus, per occupied cell, the six field components gathered (24 B) and the three current
-components written (12 B).  achieved = bytes / average launch time (HIP events on the
-simulation's stream, measured here), peak = 8 TB/s HBM3E.
+Beside it: the FP64 GPU rate of the same workload and the FP32/FP64 speedup; a roofline for the
+dominant kernel (the particle kernel) and for the whole step; a serving run (continuous batching
+of seeded uneven requests with Poisson arrivals, p50/p99 latency); the plain-C FP64 oracle timed
+on the host on a bounded sample (cpu_baseline).
+
+Algorithmic bytes (the minimum the method moves; no halos or re-reads):
+  particle kernel, per launch: per particle its state read and written (FP32: 1D/2D/3D free
+  40/48/56 B, 2D/3D bound 60/64 B, Dirac 48 B) + per occupied cell 24 B of E, B gathered and
+  12 B of J written;
+  whole step: particle kernel bytes + per cell 48 B (E, B read and written by the Yee update) +
+  per occupied cell 12 B (J read by the Yee update).
+achieved = bytes / average duration measured here with HIP events on the simulation's stream;
+peak = 8 TB/s HBM3E.  ``traffic`` is the kernel's measured HBM bytes per launch from committed
+rocprofv3 FETCH_SIZE/WRITE_SIZE runs (calibrated against a copy of known size) when those runs
+were taken on the current kernel sources with the same tile and block, else null.
 
 One GPU only: --gpus above 1 exits with a message.
 """
 from __future__ import annotations
 
 import argparse
+import copy
 import json
 import os
 import sys
@@ -31,11 +40,10 @@ METRIC = "particle-steps/s (gather+push+deposit) FP32 vs FP64 GPU; p50/p99 serve
 HBM_PEAK_GBS = 8000.0
 
 
-def particle_bytes(w, counts, es):
-    """Algorithmic bytes of one particle-kernel launch (see module docstring)."""
+def particle_bytes_per_step(w, counts, es=4):
+    """Particle state read and written per step, summed over species."""
     d = w["dims"]
     total = 0
-    occupied = set()
     for sp, n in zip(w["species"], counts):
         if sp["kind"] == "bound":
             per = (4 + d * es + 6 * es) + 6 * es  # anchor cell/offset, xi, v read; xi, v written
@@ -45,8 +53,8 @@ def particle_bytes(w, counts, es):
     return total
 
 
-def occupied_cells(sim_counts, w):
-    """Cells holding particles at load time (region cells), from the workload geometry."""
+def occupied_cells(w):
+    """Cells holding particles at load time (the species' region cells)."""
     import numpy as np
     n = w["n"]
     cells = np.zeros((n[2], n[1], n[0]), dtype=bool)
@@ -71,11 +79,18 @@ def occupied_cells(sim_counts, w):
     return int(cells.sum())
 
 
+def describe(w, npart, precision="FP32"):
+    n = "x".join(str(v) for v in w["n"][:w["dims"]])
+    sp = " + ".join(f"{s.get('ppc', 0)} ppc {s['kind']}" for s in w["species"])
+    dx = w["dx"][0] * 1e9
+    return f"{w['name']}: {w['dims']}D3V {n} cells of {dx:g} nm, {sp} ({npart} particles), {precision}"
+
+
 def run_gpu(w, precision, steps, warmup, graphs=True, time_kernels=0, block=256):
     import torch
     from paper_2501_07465_amd import pic
     sim = pic.Simulation(w, precision=precision, graphs=graphs, series_cap=steps + warmup + time_kernels + 64,
-                         block=block)
+                         block=block, unit=w.get("unit", 0))
     counts = [sim.count(s) for s in sim.species]
     sim.step(warmup)
     sim.sync()
@@ -85,11 +100,23 @@ def run_gpu(w, precision, steps, warmup, graphs=True, time_kernels=0, block=256)
     sim.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    kt = None
-    if time_kernels:
-        kt = pic.pic_time_kernels(sim.h, time_kernels)
+    kt = pic.pic_time_kernels(sim.h, time_kernels) if time_kernels else None
     fe = sim.field_energy()
-    return sim, counts, dt, kt, fe
+    del sim
+    return counts, dt, kt, fe
+
+
+def committed_traffic(workload, tile, block, unit):
+    """Traffic per launch from the committed counter summary, if it matches the current kernels."""
+    from paper_2501_07465_amd import profiling
+    path = os.path.join(ROOT, "profiles", f"traffic_k_particles_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    t = profiling.read_traffic_file(path)
+    if (t.get("source_digest") != profiling.source_digest() or t.get("tile") != "x".join(str(v) for v in tile)
+            or t.get("block") != str(block) or t.get("unit") != str(unit)):
+        return None
+    return float(t["traffic_bytes"])
 
 
 def cpu_baseline(w, budget_s):
@@ -110,6 +137,35 @@ def cpu_baseline(w, budget_s):
                       f"{el:.1f} s single-threaded plain C FP64"}
 
 
+def run_serve(n_req, scale, load, block, tile, budget_gib, slots, log, unit=None):
+    """Seeded uneven requests, Poisson arrivals at ``load`` x the measured batched capacity."""
+    import numpy as np
+    from paper_2501_07465_amd import serve, workloads as W
+    base = [W.stream_request(j, scale=scale) for j in range(n_req)]
+    # capacity: the first requests all at once
+    nprobe = min(8, n_req)
+    probe = serve.Server(dims=2, precision="fp32", hbm_budget=int(budget_gib * 2**30), max_slots=slots,
+                         block=block, tile=tile, unit=unit)
+    ps = probe.run([serve.Request(j, copy.deepcopy(base[j]), 0.0) for j in range(nprobe)])
+    del probe
+    cap = ps["particle_steps_per_s"]
+    per_req = ps["particle_steps"] / max(ps["requests"], 1)
+    lam = load * cap / per_req
+    rng = np.random.default_rng(7)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
+    arrivals -= arrivals[0]
+    srv = serve.Server(dims=2, precision="fp32", hbm_budget=int(budget_gib * 2**30), max_slots=slots,
+                       block=block, tile=tile, unit=unit)
+    reqs = [serve.Request(j, copy.deepcopy(base[j]), float(arrivals[j])) for j in range(n_req)]
+    log(f"bench: serving {n_req} requests at {lam:.1f}/s (capacity probe {cap:.3e} particle-steps/s)")
+    st = srv.run(reqs)
+    return {"requests": st["requests"], "p50_s": st["p50_s"], "p99_s": st["p99_s"], "mean_s": st["mean_s"],
+            "particle_steps_per_s": st["particle_steps_per_s"], "arrival_rate_hz": lam, "load": load,
+            "capacity_probe": cap, "grid_scale": scale, "hbm_budget_gib": budget_gib, "slots": slots,
+            "requests_desc": "seeded 2D3V disk/rod/slab requests, grid side U[128,1024] x scale, 8-32 ppc "
+                             "free + 8-32 ppc bound, 500-4000 steps, FP32"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,43 +177,84 @@ def main():
     ap.add_argument("--time-kernels", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--tile", type=str, default=None, help="particle tile, e.g. 8x8")
-    ap.add_argument("--block", type=int, default=256)
-    ap.add_argument("--copy-mib", type=int, default=0,
-                    help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--tile", type=str, default=None, help="particle tile, e.g. 16x16 (default: tuned)")
+    ap.add_argument("--block", type=int, default=None, help="particle-kernel block (default: tuned)")
+    ap.add_argument("--unit", type=int, default=None, help="particles per work unit (default: tuned; 0 = tile)")
+    ap.add_argument("--autotune", action="store_true", help="measure the tile/block/unit candidates now")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-scale", type=float, default=0.25)
+    ap.add_argument("--serve-load", type=float, default=0.75)
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--calib-mib", type=int, default=0,
+                    help="also run a float32 elementwise copy of this many MiB 3 times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_2501_07465_amd import workloads as W
+    from paper_2501_07465_amd import autotune, workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    def log(m):
+        print(m, file=sys.stderr, flush=True)
+
     w = W.WORKLOADS[args.workload]()
-    if args.tile:
-        t = [int(v) for v in args.tile.split("x")]
-        w["tile"] = t + [1] * (3 - len(t))
+    tuning = "default"
+    block = 256
+    if args.tile or args.block or args.unit is not None:
+        if args.tile:
+            t = [int(v) for v in args.tile.split("x")]
+            w["tile"] = t + [1] * (3 - len(t))
+        block = args.block or 256
+        w["unit"] = args.unit or 0
+        tuning = "explicit"
+    else:
+        res = None if args.autotune else autotune.shipped(w, "fp32")
+        tuning = "shipped"
+        if res is None:
+            log("bench: autotuning tile and block")
+            res = autotune.tune(w, "fp32", periods=2, use_cache=False, log=log)
+            tuning = "measured"
+        w = autotune.apply(w, res)
+        block = int(res["block"])
+    tile = w["tile"][:w["dims"]]
     graphs = not args.no_graphs
-    if args.copy_mib:
-        src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
+    if args.calib_mib:
+        a = torch.ones(args.calib_mib << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
-        del src, dst
-    print(f"bench: {args.workload} fp32 warmup {args.warmup} steps {args.steps}", file=sys.stderr, flush=True)
-    sim, counts, dt32, kt, fe = run_gpu(w, "fp32", args.steps, args.warmup, graphs, args.time_kernels, args.block)
+        del a, b
+    log(f"bench: {args.workload} fp32 tile {tile} block {block} warmup {args.warmup} steps {args.steps}")
+    counts, dt32, kt, fe = run_gpu(w, "fp32", args.steps, args.warmup, graphs, args.time_kernels, block)
     npart = sum(counts)
     rate32 = npart * args.steps / dt32
-    del sim
-    print(f"bench: fp32 {rate32:.3e} particle-steps/s; fp64 {args.fp64_steps} steps", file=sys.stderr, flush=True)
-    sim64, _, dt64, _, _ = run_gpu(w, "fp64", args.fp64_steps, 20, graphs, 0)
-    rate64 = npart * args.fp64_steps / dt64
-    del sim64
-    occ = occupied_cells(counts, w)
+    log(f"bench: fp32 {rate32:.3e} particle-steps/s; fp64 {args.fp64_steps} steps")
+    fp64 = None
+    if args.fp64_steps > 0:
+        # the FP64 form needs twice the LDS per window: halve the tile's longest axis until it fits
+        w64 = copy.deepcopy(w)
+        t64 = w64["tile"]
+        while autotune.lds_bytes(t64[:w["dims"]], w["dims"], "fp64", block) > autotune.LDS_BYTES:
+            a = max(range(w["dims"]), key=lambda k: t64[k])
+            t64[a] //= 2
+        _, dt64, _, _ = run_gpu(w64, "fp64", args.fp64_steps, 20, graphs, 0, block)
+        rate64 = npart * args.fp64_steps / dt64
+        fp64 = {"value": rate64, "unit": "particle-steps/s", "steps": args.fp64_steps, "tile": t64[:w["dims"]],
+                "ms_per_step": dt64 / args.fp64_steps * 1e3, "fp32_speedup": rate32 / rate64}
+    occ = occupied_cells(w)
+    ncells = 1
+    for a in range(w["dims"]):
+        ncells *= w["n"][a]
     es = 4
-    bytes_launch = particle_bytes(w, counts, es) + occ * (6 * es + 3 * es)
+    bytes_particle = particle_bytes_per_step(w, counts, es) + occ * (6 * es + 3 * es)
+    bytes_step = bytes_particle + ncells * 12 * es + occ * 3 * es
     t_particle_ms = float(kt[0])
-    achieved = bytes_launch / (t_particle_ms * 1e-3) / 1e9
+    achieved = bytes_particle / (t_particle_ms * 1e-3) / 1e9
+    ms_step = dt32 / args.steps * 1e3
+    step_gbs = bytes_step / (ms_step * 1e-3) / 1e9
     line = {
         "metric": METRIC,
         "value": rate32,
@@ -165,25 +262,31 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt32 / args.steps * 1e3,
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{w['name']}: 2D3V {w['n'][0]}x{w['n'][1]} cells of 1 nm, disk radius 100 cells, "
-                               f"16 ppc FD free + 16 ppc bound ({npart} particles), 800 nm pulse, FP32",
-                   "particles": npart, "graphs": graphs, "tile": w["tile"], "block": args.block},
-        "fp64": {"value": rate64, "unit": "particle-steps/s", "steps": args.fp64_steps,
-                 "ms_per_step": dt64 / args.fp64_steps * 1e3, "fp32_speedup": rate32 / rate64},
-        "kernels_ms": {"particles": t_particle_ms, "fields": float(kt[1]), "sort": float(kt[2])},
+        "config": {"workload": describe(w, npart), "particles": npart, "cells": ncells, "occupied_cells": occ,
+                   "graphs": graphs, "tile": tile, "block": block, "unit": w.get("unit", 0), "tuning": tuning,
+                   "sort_every": 20},
+        "fp64": fp64,
+        "kernels_ms": {"particles": t_particle_ms, "fields": float(kt[1]), "sort_per_sort": float(kt[2]),
+                       "particle_kernel_rate": npart / (t_particle_ms * 1e-3)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_particles<2,float>", "bytes_per_launch": bytes_launch},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": committed_traffic(args.workload, tile, block, w.get("unit", 0)),
+                     "kernel": f"k_particles<{w['dims']},float>", "bytes_per_launch": bytes_particle},
+        "step_roofline": {"bytes_per_step": bytes_step, "achieved": step_gbs, "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS},
         "field_energy_end": fe,
     }
+    if args.serve_requests > 0:
+        line["serve"] = run_serve(args.serve_requests, args.serve_scale, args.serve_load, block,
+                                  None, args.serve_budget_gib, args.serve_slots, log, w.get("unit", 0))
     if not args.no_cpu:
-        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        log("bench: cpu baseline")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(line))
 

@@ -64,6 +64,9 @@ typedef struct {
     int precision;      /* PIC_FP32 or PIC_FP64 for positions, fields, push and deposit  */
     int tile[3];        /* particle tile shape, powers of two (inactive axes 1)          */
     int block;          /* threads per particle-kernel workgroup: 64, 128, 256 or 512    */
+    int unit;           /* most particles one particle-kernel workgroup takes from a tile */
+                        /* (a tile's particles are split into units of at most this many; */
+                        /* 0: one unit per tile; otherwise >= 64)                         */
     int sort_every;     /* cell sort every this many steps (>= 1)                        */
     int series_cap;     /* steps of the current time series kept on the device           */
     int track_continuity; /* 1: measure the continuity residual on every step (slower)   */

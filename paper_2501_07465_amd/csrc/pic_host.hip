@@ -145,7 +145,9 @@ static int setup_grid(pic_sim* s)
     if (g.block != 64 && g.block != 128 && g.block != 256 && g.block != 512)
         return fail(s, PIC_EINVAL, "block must be 64, 128, 256 or 512");
     if (g.series_cap <= 0) g.series_cap = 8192;
+    if (g.unit < 0 || (g.unit > 0 && g.unit < 64)) return fail(s, PIC_EINVAL, "unit must be 0 or >= 64");
     memset(&h, 0, sizeof(h));
+    h.unit_cap = g.unit;
     h.dims = g.dims;
     h.precision = g.precision;
     s->es = g.precision == PIC_FP32 ? 4 : 8;
@@ -199,7 +201,7 @@ static int setup_grid(pic_sim* s)
     s->passes = (bits + 7) / 8;
     h.Vf = h.Wf[0] * h.Wf[1] * h.Wf[2];
     h.Vj = h.Wj[0] * h.Wj[1] * h.Wj[2];
-    const size_t plds = (size_t)s->es * (6 * (size_t)h.Vf + 3 * (size_t)h.Vj);
+    const size_t plds = (size_t)s->es * (6 * (size_t)h.Vf + 3 * (size_t)h.Vj + (size_t)kStrayScratch * (g.block / 64));
     if (plds > 65536) return fail(s, PIC_EINVAL, "particle tile needs %zu bytes of LDS (> 64 KiB)", plds);
     // field tiles
     const int ft[3][3] = {{FieldTile<1>::X, FieldTile<1>::Y, FieldTile<1>::Z},
@@ -475,15 +477,26 @@ static size_t plan(pic_sim* s, char* base, bool assign)
     for (int p = 0; p < 2; ++p) h.jover[p] = P.takeb(3 * L * es);
     s->max_slots = count_slot_tiles(s);
     h.max_slots = s->max_slots;
-    h.slots = P.takeb((size_t)s->max_slots * 3 * h.Vj * es);
+    // units of a tile: ceil(c_t / U) <= c_t / U + 1, so all units <= ceil(N / U) + active tiles
+    long long max_units = s->max_slots;
+    if (h.unit_cap > 0) {
+        long long ntot = 0;
+        for (auto& x : s->sp) ntot += x.n;
+        max_units += (ntot + h.unit_cap - 1) / h.unit_cap;
+    }
+    h.max_units = (int)std::min<long long>(max_units, 1LL << 30);
+    h.slots = P.takeb((size_t)h.max_units * 3 * h.Vj * es);
     h.tile_slot = P.take<int>(h.ntiles);
+    h.tile_nslot = P.take<int>(h.ntiles);
     h.active = P.take<int>(h.ntiles);
     h.n_active = P.take<int>(1);
+    h.units = P.take<int>((size_t)h.max_units * 3);
+    h.n_units = P.take<int>(1);
     h.step_p = P.take<long long>(1);
     h.step_f = P.take<long long>(1);
     h.over_stamp = P.take<long long>(2);
     h.over_count = P.take<unsigned long long>(1);
-    h.partials = P.take<double>((size_t)s->max_slots * 3);
+    h.partials = P.take<double>((size_t)h.max_units * 3);
     h.series = P.take<double>((size_t)h.series_cap * 3);
     h.rho_ion = P.take<double>(L);
     h.rho_a = P.take<double>(L);
@@ -493,9 +506,8 @@ static size_t plan(pic_sim* s, char* base, bool assign)
     s->part = P.take<double>(kDiagBlocks * 4);
     s->outv = P.take<double>(16);
     s->cont = P.take<double>(2);
-    long long nmax = 1;
-    for (auto& x : s->sp) nmax = std::max(nmax, x.n);
-    const long long nb = (nmax + kSortIpb - 1) / kSortIpb;
+    long long nb = 1;
+    for (auto& x : s->sp) nb = std::max(nb, (x.n + sort_ipb(x.n) - 1) / sort_ipb(x.n));
     h.sort_hist = P.take<int>((size_t)256 * nb);
     h.nspecies = (int)s->sp.size();
     for (size_t i = 0; i < s->sp.size(); ++i) {
@@ -619,7 +631,8 @@ extern "C" int pic_bind(pic_sim* s, void* dev_arena, size_t bytes, void* hip_str
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
     }
-    s->pgrid = std::max(1, std::min(s->max_slots, ncu * 8));
+    // persistent particle grid: a multiple of 8 (the XCD count) up to 8 workgroups per CU
+    s->pgrid = std::max(8, (std::min(s->h.max_units, ncu * 8) + 7) / 8 * 8);
     HIPCHK(s, enqueue_fill(s->arena, need - kAlign, s->st));
     int r = upload_table(s);
     if (r) return r;

@@ -30,6 +30,10 @@ enum Region { R_ALL = 0, R_BALL = 1, R_BOX = 2 };
 // c0-1..c0+1 of the start cell c0; the charge-conserving deposit writes nodes
 // c0-1..c0+2.  Hence the field window spans [lo-2, hi+2] and the current
 // window [lo-2, hi+3].
+// Per-wavefront LDS scratch of the particle kernel (values): the global gather of a particle
+// outside its tile window stages 6 components x 2^3 nodes there.
+constexpr int kStrayScratch = 48;
+
 // Field-kernel tile (cells) per number of active axes: x, y, z.
 template <int DIM>
 struct FieldTile;
@@ -87,16 +91,22 @@ struct SimDev {
     // fields, planar [comp][z][y][x], R; two buffers: step n reads [n & 1] and writes [(n+1) & 1]
     void* E[2][3];
     void* B[2][3];
-    void* slots;           // per active tile: [3][Vj] current window
-    int* tile_slot;        // [ntiles]: slot of an active tile, -1 otherwise
+    void* slots;           // per work unit: [3][Vj] current window
+    int* tile_slot;        // [ntiles]: first unit (slot) of an active tile, -1 otherwise
+    int* tile_nslot;       // [ntiles]: units of an active tile (consecutive slots)
     int* active;           // [ntiles]: active tile list
     int* n_active;         // device scalar
-    int max_slots;         // capacity of the slot array (tiles that can hold particles)
+    int max_slots;         // capacity of the active list (tiles that can hold particles)
+    int* units;            // [max_units][3]: tile, first and end particle in the tile's
+                           // species-concatenated order
+    int* n_units;          // device scalar
+    int max_units;         // capacity of the unit list and of the slot array
+    int unit_cap;          // most particles per unit (0: one unit per tile)
     int* sort_hist;        // radix-sort digit histogram scratch
     void* jover[2];        // [3][Lvol] current of particles outside their window (rare)
     long long* over_stamp; // [2] step+1 of the last overflow per parity
     unsigned long long* over_count;
-    double* partials;      // [ntiles][3] per active tile: sum q w v_{n+1/2}
+    double* partials;      // [max_units][3] per unit: sum q w v_{n+1/2}
     double* series;        // [series_cap][3]
     int series_cap;
     long long* step_p;     // steps pushed (written by the particle kernel)

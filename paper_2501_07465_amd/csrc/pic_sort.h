@@ -4,7 +4,14 @@
 
 namespace pic {
 
-constexpr int kSortIpb = 4096;  // keys per radix-sort block
+// Keys per radix-sort block: 4096, doubled until at most 4096 blocks cover n keys (the digit
+// histogram holds 256 counts per block).
+inline int sort_ipb(long long n)
+{
+    long long ipb = 4096;
+    while ((n + ipb - 1) / ipb > 4096) ipb *= 2;
+    return (int)ipb;
+}
 
 // Stable radix sort of species s by cell key (passes of 8 bits), permutation of its arrays
 // into the alternates and pointer swap.  elem = 4 (FP32 form) or 8 (FP64 form).

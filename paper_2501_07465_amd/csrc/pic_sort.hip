@@ -5,6 +5,7 @@
 // input order (wavefront multisplit with ballots, then waves in order, then blocks in order).
 // All kernels read their arrays through the device SimDev table, so a captured graph stays
 // valid when the array pointers are swapped after each sort.
+#include "pic_dpp.h"
 #include "pic_internal.h"
 #include "pic_sort.h"
 
@@ -12,7 +13,7 @@ namespace pic {
 
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
-constexpr int kSortBlock = 256;
+constexpr int kSortBlock = 1024;
 
 // keys[i] = tile-major key of particle i's cell (anchor cell for bound particles); vals[i] = i
 __global__ void k_keys(SimDev* __restrict__ S, int s)
@@ -48,31 +49,56 @@ __global__ void __launch_bounds__(kSortBlock) k_radix_hist(SimDev* __restrict__ 
         for (int d = threadIdx.x; d < kRadix; d += blockDim.x) S->sort_hist[d * nb + b] = h[d];
 }
 
-// exclusive scan of hist[0 .. kRadix * nb) by one block
-__global__ void __launch_bounds__(1024) k_radix_scan(SimDev* __restrict__ S, int s, int ipb)
+// exclusive scan of hist[0 .. kRadix * nb) by one block.  Wave w owns a contiguous segment; its
+// lanes read it 64 consecutive entries at a time (coalesced), kScanGroup rows in flight.  Pass 1
+// sums each segment, pass 2 scans it row by row (DPP wavefront scan) with the segment's offset
+// carried in.
+constexpr int kScanThreads = 1024;
+constexpr int kScanGroup = 16;
+
+__global__ void __launch_bounds__(kScanThreads) k_radix_scan(SimDev* __restrict__ S, int s, int ipb)
 {
-    __shared__ int part[1024];
+    constexpr int NW = kScanThreads / 64;
+    __shared__ int wsum[NW];
     const int n = S->sp[s].n;
     const int nb = (n + ipb - 1) / ipb;
     const int total = kRadix * nb;
     int* H = S->sort_hist;
-    const int per = (total + blockDim.x - 1) / blockDim.x;
-    const int lo = threadIdx.x * per, hi = min(total, lo + per);
-    int sum = 0;
-    for (int i = lo; i < hi; ++i) sum += H[i];
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-        int v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int per_w = (total + NW * 64 - 1) / (NW * 64) * 64;
+    const int w0 = min(total, wave * per_w), w1 = min(total, w0 + per_w);
+    int acc = 0;
+    for (int g = w0; g < w1; g += 64 * kScanGroup) {
+        int v[kScanGroup];
+#pragma unroll
+        for (int k = 0; k < kScanGroup; ++k) {
+            const int i = g + k * 64 + lane;
+            v[k] = i < w1 ? H[i] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kScanGroup; ++k) acc += v[k];
     }
-    int run = part[threadIdx.x] - sum;
-    for (int i = lo; i < hi; ++i) {
-        const int v = H[i];
-        H[i] = run;
-        run += v;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) wsum[wave] = acc;
+    __syncthreads();
+    int carry = 0;
+    for (int w = 0; w < wave; ++w) carry += wsum[w];
+    const unsigned msk = scan_masks(lane);
+    for (int g = w0; g < w1; g += 64 * kScanGroup) {
+        int v[kScanGroup];
+#pragma unroll
+        for (int k = 0; k < kScanGroup; ++k) {
+            const int i = g + k * 64 + lane;
+            v[k] = i < w1 ? H[i] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kScanGroup; ++k) {
+            const int inc = seg_scan<int>(v[k], msk);
+            const int i = g + k * 64 + lane;
+            if (i < w1) H[i] = carry + inc - v[k];
+            carry += __builtin_amdgcn_readlane(inc, 63);
+        }
     }
 }
 
@@ -201,60 +227,85 @@ __global__ void k_tile_ranges(SimDev* __restrict__ S, int s, int passes)
     }
 }
 
-// Active tiles (any species has particles) in tile order, their slots, and the count.
+// Active tiles (any species has particles) in tile order, and their work units: a tile holding
+// c particles (all species) gets ceil(c / U) units of at most U particles, in its species-
+// concatenated order (one unit when U is 0); the units of a tile take consecutive slots.
 __global__ void __launch_bounds__(1024) k_compact(SimDev* __restrict__ S)
 {
-    __shared__ int part[1024];
+    __shared__ int wa[16], wu[16];
     const int nt = S->ntiles;
+    const int U = S->unit_cap;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     const int per = (nt + blockDim.x - 1) / blockDim.x;
-    const int lo = threadIdx.x * per, hi = min(nt, lo + per);
-    auto active = [&](int t) {
-        for (int s = 0; s < S->nspecies; ++s)
-            if (S->sp[s].tile_start[t + 1] > S->sp[s].tile_start[t]) return true;
-        return false;
+    const int lo = min(nt, tid * per), hi = min(nt, lo + per);
+    auto count = [&](int t) {
+        int c = 0;
+        for (int s = 0; s < S->nspecies; ++s) c += S->sp[s].tile_start[t + 1] - S->sp[s].tile_start[t];
+        return c;
     };
-    int cnt = 0;
-    for (int t = lo; t < hi; ++t) cnt += active(t) ? 1 : 0;
-    part[threadIdx.x] = cnt;
-    __syncthreads();
-    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-        int v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    int run = part[threadIdx.x] - cnt;
+    auto nunits = [&](int c) { return c == 0 ? 0 : (U > 0 ? (c + U - 1) / U : 1); };
+    int ca = 0, cu = 0;
     for (int t = lo; t < hi; ++t) {
-        if (active(t)) {
-            if (run < S->max_slots) {
-                S->active[run] = t;
-                S->tile_slot[t] = run;
-            } else {
-                S->tile_slot[t] = -1;
+        const int c = count(t);
+        ca += c > 0 ? 1 : 0;
+        cu += nunits(c);
+    }
+    // exclusive prefixes of the active-tile and unit counts over threads
+    int ia = ca, iu = cu;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int ta = __shfl_up(ia, off, 64), tu = __shfl_up(iu, off, 64);
+        if (lane >= off) { ia += ta; iu += tu; }
+    }
+    if (lane == 63) { wa[wave] = ia; wu[wave] = iu; }
+    __syncthreads();
+    int ba = 0, bu = 0, ta = 0, tu = 0;
+    for (int w = 0; w < nw; ++w) {
+        if (w < wave) { ba += wa[w]; bu += wu[w]; }
+        ta += wa[w];
+        tu += wu[w];
+    }
+    // a list that does not fit (particles in tiles the capacity did not count) is dropped whole
+    // and flagged: no particle moves this period
+    const bool fits = ta <= S->max_slots && tu <= S->max_units;
+    int ra = ba + ia - ca, ru = bu + iu - cu;
+    for (int t = lo; t < hi; ++t) {
+        const int c = count(t);
+        if (c > 0 && fits) {
+            const int k = nunits(c);
+            S->active[ra] = t;
+            S->tile_slot[t] = ru;
+            S->tile_nslot[t] = k;
+            for (int j = 0; j < k; ++j) {
+                int* u = S->units + 3 * (ru + j);
+                u[0] = t;
+                u[1] = U > 0 ? j * U : 0;
+                u[2] = U > 0 ? min(c, (j + 1) * U) : c;
             }
-            ++run;
+            ++ra;
+            ru += k;
         } else {
             S->tile_slot[t] = -1;
+            S->tile_nslot[t] = 0;
         }
     }
-    if (threadIdx.x == blockDim.x - 1) {
-        const int total = part[blockDim.x - 1];
-        *S->n_active = total < S->max_slots ? total : S->max_slots;
-        if (total > S->max_slots) atomicAdd(S->over_count, 1ull << 40);
+    if (tid == 0) {
+        *S->n_active = fits ? ta : 0;
+        *S->n_units = fits ? tu : 0;
+        if (!fits) atomicAdd(S->over_count, 1ull << 40);
     }
 }
 
 // --------------------------------------------------------------------------------------------
 hipError_t enqueue_sort(SimDev* dS, int s, int n, int passes, int elem, hipStream_t st)
 {
-    const int ipb = kSortIpb;
+    const int ipb = sort_ipb(n);
     const int nb = (n + ipb - 1) / ipb;
     const int g = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
     if (n > 0) {
         hipLaunchKernelGGL(k_keys, dim3(g > 0 ? g : 1), dim3(256), 0, st, dS, s);
         for (int p = 0; p < passes; ++p) {
             hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortBlock), 0, st, dS, s, p, ipb);
-            hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, st, dS, s, ipb);
+            hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(kScanThreads), 0, st, dS, s, ipb);
             hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortBlock), 0, st, dS, s, p, ipb);
         }
         hipLaunchKernelGGL(k_permute, dim3(g > 0 ? g : 1), dim3(256), 0, st, dS, s, passes, elem);

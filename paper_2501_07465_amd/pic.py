@@ -42,6 +42,7 @@ EXPORTED = ["pic_create", "pic_init_species", "pic_footprint", "pic_bind", "pic_
 class GridDesc(C.Structure):
     _fields_ = [("dims", C.c_int), ("n", C.c_int * 3), ("dx", C.c_double * 3), ("dt", C.c_double),
                 ("bc", C.c_int * 3), ("precision", C.c_int), ("tile", C.c_int * 3), ("block", C.c_int),
+                ("unit", C.c_int),
                 ("sort_every", C.c_int), ("series_cap", C.c_int), ("track_continuity", C.c_int),
                 ("src_kind", C.c_int), ("src_comp", C.c_int), ("src_axis", C.c_int),
                 ("src_index", C.c_int * 3), ("src_j0", C.c_double), ("src_omega", C.c_double),
@@ -252,7 +253,7 @@ _SRC = {"none": PIC_SRC_NONE, "sheet": PIC_SRC_SHEET, "point": PIC_SRC_POINT}
 
 
 def grid_desc(w: dict, precision: str | None = None, track_continuity: bool = False, block: int = 256,
-              series_cap: int | None = None) -> GridDesc:
+              series_cap: int | None = None, unit: int | None = None) -> GridDesc:
     g = GridDesc()
     g.dims = w["dims"]
     for a in range(3):
@@ -264,6 +265,7 @@ def grid_desc(w: dict, precision: str | None = None, track_continuity: bool = Fa
     prec = precision or w.get("precision", "fp32")
     g.precision = PIC_FP64 if prec == "fp64" else PIC_FP32
     g.block = block
+    g.unit = int(w.get("unit", 0) if unit is None else unit)
     g.sort_every = w.get("sort_every", 20)
     g.series_cap = series_cap or max(1, int(w.get("steps", 1000)) + 64)
     g.track_continuity = int(track_continuity)
@@ -323,11 +325,11 @@ class Simulation:
     """One device-resident simulation: descriptors from a workload dict, arena and stream from torch."""
 
     def __init__(self, w: dict, precision: str | None = None, states=None, fields=None, init_fields=True,
-                 track_continuity=False, graphs=True, stream=None, block=256, series_cap=None):
+                 track_continuity=False, graphs=True, stream=None, block=256, series_cap=None, unit=None):
         import torch
         self.w = w
         self.h = None
-        g = grid_desc(w, precision, track_continuity, block, series_cap)
+        g = grid_desc(w, precision, track_continuity, block, series_cap, unit)
         self.h = pic_create(g)
         self.species = []
         for i, sp in enumerate(w["species"]):
@@ -458,9 +460,10 @@ class Batch:
             self.b = None
 
 
-def footprint_of(w: dict, precision: str | None = None, block: int = 256, series_cap: int | None = None) -> int:
+def footprint_of(w: dict, precision: str | None = None, block: int = 256, series_cap: int | None = None,
+                 unit: int | None = None) -> int:
     """Device bytes a simulation of workload ``w`` needs (host-only planning, nothing allocated)."""
-    h = pic_create(grid_desc(w, precision, False, block, series_cap))
+    h = pic_create(grid_desc(w, precision, False, block, series_cap, unit))
     try:
         for sp in w["species"]:
             pic_init_species(h, species_desc(sp), w.get("seed", 1))

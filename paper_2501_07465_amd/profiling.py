@@ -1,0 +1,152 @@
+"""Summaries of rocprofv3 output: per-kernel durations, per-dispatch HBM counters, and the HBM
+traffic of one kernel calibrated against an elementwise copy of known size.
+
+Inputs are the CSV files rocprofv3 writes with ``--output-format csv``:
+``*_kernel_stats.csv`` (from ``--kernel-trace --stats``) and ``*_counter_collection.csv`` (from
+``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``, one counter per run; values in KiB per dispatch).
+
+The calibration kernel is the float32 elementwise multiply that ``bench.py --calib-mib M`` runs
+three times: it reads and writes exactly M MiB, so the factor M * 1024 / (KiB counted) turns the
+counted KiB of any kernel in the same run into bytes.
+
+    python -m paper_2501_07465_amd.profiling traffic --fetch DIR --write DIR --kernel NAME \
+        --calib-mib M --out FILE --command "..."
+    python -m paper_2501_07465_amd.profiling stats --trace DIR --out FILE --command "..."
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CALIB_KERNEL = "elementwise"  # torch's vectorized elementwise kernel of the calibration multiply
+KERNEL_SOURCES = ("csrc/pic_kernels.inc", "csrc/pic_internal.h", "csrc/pic_k32.hip", "csrc/pic_k64.hip")
+
+
+def source_digest() -> str:
+    """SHA-256 over the sources of the particle and field kernels (counters go stale when it changes)."""
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _one(pattern_dir: str, suffix: str) -> str:
+    hits = sorted(glob.glob(os.path.join(pattern_dir, "**", f"*{suffix}"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {pattern_dir}")
+    return hits[0]
+
+
+def kernel_stats(trace_dir: str) -> list[dict]:
+    rows = []
+    with open(_one(trace_dir, "_kernel_stats.csv")) as f:
+        for r in csv.DictReader(f):
+            rows.append({"name": r["Name"], "calls": int(r["Calls"]), "total_ns": float(r["TotalDurationNs"]),
+                         "avg_ns": float(r["AverageNs"]), "pct": float(r["Percentage"]),
+                         "min_ns": float(r["MinNs"]), "max_ns": float(r["MaxNs"])})
+    rows.sort(key=lambda r: -r["total_ns"])
+    return rows
+
+
+def counter_per_dispatch(run_dir: str, counter: str) -> dict:
+    """kernel name -> list of counter values, one per dispatch."""
+    out = collections.defaultdict(list)
+    with open(_one(run_dir, "_counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter:
+                out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return out
+
+
+def _match(d: dict, sub: str) -> list:
+    vals = []
+    for k, v in d.items():
+        if sub in k:
+            vals.extend(v)
+    if not vals:
+        raise KeyError(f"no dispatch of a kernel matching {sub!r}")
+    return vals
+
+
+def traffic(fetch_dir: str, write_dir: str, kernel: str, calib_mib: float) -> dict:
+    fetch = counter_per_dispatch(fetch_dir, "FETCH_SIZE")
+    write = counter_per_dispatch(write_dir, "WRITE_SIZE")
+    kf, kw = _match(fetch, kernel), _match(write, kernel)
+    cf, cw = _match(fetch, CALIB_KERNEL), _match(write, CALIB_KERNEL)
+    ref_kib = calib_mib * 1024.0
+    f_factor = ref_kib / (sum(cf) / len(cf))
+    w_factor = ref_kib / (sum(cw) / len(cw))
+    fetch_b = sum(kf) / len(kf) * 1024.0 * f_factor
+    write_b = sum(kw) / len(kw) * 1024.0 * w_factor
+    return {"kernel": kernel, "dispatches": len(kf), "fetch_kib": sum(kf) / len(kf), "write_kib": sum(kw) / len(kw),
+            "calib_fetch_kib": sum(cf) / len(cf), "calib_write_kib": sum(cw) / len(cw), "calib_mib": calib_mib,
+            "fetch_factor": f_factor, "write_factor": w_factor, "fetch_bytes": fetch_b, "write_bytes": write_b,
+            "traffic_bytes": fetch_b + write_b}
+
+
+def read_traffic_file(path: str) -> dict:
+    """key = value lines of a traffic summary (values as text)."""
+    out = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                out[k.strip()] = v.strip()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--calib-mib", type=float, required=True)
+    t.add_argument("--workload", required=True)
+    t.add_argument("--tile", required=True)
+    t.add_argument("--block", required=True)
+    t.add_argument("--unit", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--command", action="append", default=[])
+    s = sub.add_parser("stats")
+    s.add_argument("--trace", required=True)
+    s.add_argument("--out", required=True)
+    s.add_argument("--command", action="append", default=[])
+    s.add_argument("--top", type=int, default=16)
+    a = ap.parse_args()
+    if a.cmd == "traffic":
+        r = traffic(a.fetch, a.write, a.kernel, a.calib_mib)
+        with open(a.out, "w") as f:
+            f.write(f"# HBM traffic per dispatch of {a.kernel} on {a.workload} (rocprofv3 FETCH_SIZE, WRITE_SIZE)\n")
+            for c in a.command:
+                f.write(f"# command: {c}\n")
+            f.write("# calibration: float32 elementwise multiply reading and writing calib_mib MiB; "
+                    "factor = calib bytes / counted bytes\n")
+            f.write(f"workload = {a.workload}\ntile = {a.tile}\nblock = {a.block}\nunit = {a.unit}\n"
+                    f"source_digest = {source_digest()}\n")
+            for k, v in r.items():
+                f.write(f"{k} = {v}\n")
+        print(open(a.out).read())
+    else:
+        rows = kernel_stats(a.trace)
+        with open(a.out, "w") as f:
+            f.write("# rocprofv3 --kernel-trace --stats summary\n")
+            for c in a.command:
+                f.write(f"# command: {c}\n")
+            f.write(f"# source_digest = {source_digest()}\n")
+            f.write(f"{'kernel':80s} {'calls':>7s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}\n")
+            for r in rows[:a.top]:
+                f.write(f"{r['name'][:80]:80s} {r['calls']:7d} {r['avg_ns'] / 1e3:10.2f} {r['min_ns'] / 1e3:10.2f} "
+                        f"{r['max_ns'] / 1e3:10.2f} {r['pct']:6.2f}\n")
+        print(open(a.out).read())
+
+
+if __name__ == "__main__":
+    main()

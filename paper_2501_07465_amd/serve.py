@@ -41,7 +41,7 @@ class Server:
     """Admission by HBM footprint and slot count, continuous batching, per-request results."""
 
     def __init__(self, dims: int = 2, precision: str = "fp32", hbm_budget: int = 16 << 30, max_slots: int = 64,
-                 block: int = 512, sort_every: int = 20, tile=None, max_ahead: int = 2):
+                 block: int = 512, sort_every: int = 20, tile=None, max_ahead: int = 2, unit: int | None = None):
         self.dims = dims
         self.precision = precision
         self.budget = int(hbm_budget)
@@ -49,6 +49,7 @@ class Server:
         self.block = block
         self.period = sort_every
         self.tile = tile
+        self.unit = unit
         self.max_ahead = max_ahead
         self.batch = self._make_batch(max_slots, dims, precision)
         self.used = 0
@@ -65,11 +66,11 @@ class Server:
             raise ValueError("request dimensionality differs from the server's")
         if w.get("sort_every", 20) != self.period or r.steps % self.period:
             raise ValueError("request steps must be whole sort periods of the server")
-        r.footprint = pic.footprint_of(w, self.precision, self.block, series_cap=r.steps + 64)
+        r.footprint = pic.footprint_of(w, self.precision, self.block, series_cap=r.steps + 64, unit=self.unit)
 
     def _admit(self, r: Request, now: float):
         r.sim = pic.Simulation(r.w, precision=self.precision, graphs=False, stream=self.batch.stream,
-                               block=self.block, series_cap=r.steps + 64)
+                               block=self.block, series_cap=r.steps + 64, unit=self.unit)
         r.particles = sum(r.sim.count(s) for s in r.sim.species)
         self.batch.add(r.sim)
         self.used += r.footprint

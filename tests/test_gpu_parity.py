@@ -223,3 +223,16 @@ def test_overflow_path_long_sort_period(oracle):
     ref.step(30)
     assert sim.overflow() > 0
     _compare(sim, ref, w, 1e-12, "fp64 overflow")
+
+
+@pytest.mark.parametrize("name,unit", [("disk2d", 64), ("disk2d", 200), ("sheet2d", 96), ("sphere3d", 128)])
+def test_fp64_tiles_split_into_units(oracle, name, unit):
+    """Tiles whose particles are split over several blocks (one current slot per unit) stay exact."""
+    from paper_2501_07465_amd import pic
+    w = _small(name)
+    print(f"case fp64 units {name} unit {unit}", flush=True)
+    ref = oracle.build_workload(w)
+    sim = pic.Simulation(w, precision="fp64", states=ref.state(), fields=ref.fields(), graphs=True, unit=unit)
+    sim.step(40)
+    ref.step(40)
+    _compare(sim, ref, w, 1e-12, f"fp64 units {name}")
