@@ -12,6 +12,7 @@ counted KiB of any kernel in the same run into bytes.
     python -m paper_2501_07465_amd.profiling traffic --fetch DIR --write DIR --kernel NAME \
         --calib-mib M --out FILE --command "..."
     python -m paper_2501_07465_amd.profiling stats --trace DIR --out FILE --command "..."
+    python -m paper_2501_07465_amd.profiling counters --run DIR --kernel NAME --out FILE --command "..."
 """
 from __future__ import annotations
 
@@ -90,6 +91,25 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, calib_mib: float) -> di
             "traffic_bytes": fetch_b + write_b}
 
 
+def counter_summary(run_dir: str, kernels: list[str]) -> dict:
+    """Per-dispatch averages of every counter in a counter-collection run, for matching kernels."""
+    out = {}
+    with open(_one(run_dir, "_counter_collection.csv")) as f:
+        rows = list(csv.DictReader(f))
+    for sub in kernels:
+        acc = collections.defaultdict(list)
+        meta = None
+        for r in rows:
+            if sub in r["Kernel_Name"]:
+                acc[r["Counter_Name"]].append(float(r["Counter_Value"]))
+                meta = {"grid": r["Grid_Size"], "workgroup": r["Workgroup_Size"], "vgpr": r["VGPR_Count"],
+                        "lds": r["LDS_Block_Size"]}
+        if acc:
+            out[sub] = {"meta": meta, "counters": {c: sum(v) / len(v) for c, v in acc.items()},
+                        "dispatches": max(len(v) for v in acc.values())}
+    return out
+
+
 def read_traffic_file(path: str) -> dict:
     """key = value lines of a traffic summary (values as text)."""
     out = {}
@@ -115,6 +135,11 @@ def main():
     t.add_argument("--unit", required=True)
     t.add_argument("--out", required=True)
     t.add_argument("--command", action="append", default=[])
+    c = sub.add_parser("counters")
+    c.add_argument("--run", required=True)
+    c.add_argument("--kernel", action="append", required=True)
+    c.add_argument("--out", required=True)
+    c.add_argument("--command", action="append", default=[])
     s = sub.add_parser("stats")
     s.add_argument("--trace", required=True)
     s.add_argument("--out", required=True)
@@ -133,6 +158,18 @@ def main():
                     f"source_digest = {source_digest()}\n")
             for k, v in r.items():
                 f.write(f"{k} = {v}\n")
+        print(open(a.out).read())
+    elif a.cmd == "counters":
+        r = counter_summary(a.run, a.kernel)
+        with open(a.out, "w") as f:
+            f.write("# rocprofv3 --pmc counters, average per dispatch\n")
+            for cmd in a.command:
+                f.write(f"# command: {cmd}\n")
+            f.write(f"# source_digest = {source_digest()}\n")
+            for k, v in r.items():
+                f.write(f"\n[{k}] dispatches {v['dispatches']} {v['meta']}\n")
+                for cn, cv in sorted(v["counters"].items()):
+                    f.write(f"{cn} = {cv:.1f}\n")
         print(open(a.out).read())
     else:
         rows = kernel_stats(a.trace)
