@@ -921,40 +921,54 @@ extern "C" int pic_time_kernels(pic_sim* s, int nsteps, double out[4])
     if (!s || !out) return PIC_EINVAL;
     if (!s->bound) return fail(s, PIC_ESTATE, "bind first");
     if (s->batch_refs) return fail(s, PIC_ESTATE, "simulation is in a batch");
-    hipEvent_t ev[6];
-    for (auto& e : ev) HIPCHK(s, hipEventCreate(&e));
-    double tp = 0.0, tf = 0.0, ts = 0.0;
-    int nsort = 0, r = PIC_OK;
+    if (nsteps < 0) return PIC_EINVAL;
+    // five events per step (sort start/end, particles start, fields start, fields end), all
+    // recorded back to back on the simulation's stream and read after one synchronisation, so
+    // that no host round trip falls between a kernel and its events
+    std::vector<hipEvent_t> ev((size_t)5 * nsteps, nullptr);
+    std::vector<char> sorted((size_t)nsteps, 0);
+    int r = PIC_OK;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) { r = fail(s, PIC_EDEVICE, "event create"); break; }
     for (int k = 0; k < nsteps && !r; ++k) {
+        hipEvent_t* e = &ev[(size_t)5 * k];
         const bool sort = s->need_sort || s->step % s->g.sort_every == 0;
+        hipError_t x = hipSuccess;
         if (sort) {
-            if ((r = (hipEventRecord(ev[4], s->st) == hipSuccess ? PIC_OK : PIC_EDEVICE))) break;
-            if ((r = enqueue_sort_all(s, nullptr))) break;
-            if ((r = (hipEventRecord(ev[5], s->st) == hipSuccess ? PIC_OK : PIC_EDEVICE))) break;
+            sorted[k] = 1;
+            x = hipEventRecord(e[0], s->st);
+            if (x == hipSuccess && (r = enqueue_sort_all(s, nullptr))) break;
+            if (x == hipSuccess) x = hipEventRecord(e[1], s->st);
         }
         const Launch L = make_launch(s);
-        hipError_t e = hipEventRecord(ev[0], s->st);
-        if (e == hipSuccess) e = s->g.precision == PIC_FP32 ? Launchers<float>::particles(s->g.dims, L)
+        if (x == hipSuccess) x = hipEventRecord(e[2], s->st);
+        if (x == hipSuccess) x = s->g.precision == PIC_FP32 ? Launchers<float>::particles(s->g.dims, L)
                                                             : Launchers<double>::particles(s->g.dims, L);
-        if (e == hipSuccess) e = hipEventRecord(ev[1], s->st);
-        if (e == hipSuccess) e = s->g.precision == PIC_FP32 ? Launchers<float>::fields(s->g.dims, L, s->field_lds)
+        if (x == hipSuccess) x = hipEventRecord(e[3], s->st);
+        if (x == hipSuccess) x = s->g.precision == PIC_FP32 ? Launchers<float>::fields(s->g.dims, L, s->field_lds)
                                                             : Launchers<double>::fields(s->g.dims, L, s->field_lds);
-        if (e == hipSuccess) e = hipEventRecord(ev[2], s->st);
-        if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
-        if (e != hipSuccess) { r = fail(s, PIC_EDEVICE, "timing: %s", hipGetErrorString(e)); break; }
+        if (x == hipSuccess) x = hipEventRecord(e[4], s->st);
+        if (x != hipSuccess) { r = fail(s, PIC_EDEVICE, "timing: %s", hipGetErrorString(x)); break; }
+        s->step++;
+    }
+    double tp = 0.0, tf = 0.0, ts = 0.0;
+    int nsort = 0;
+    if (!r && hipStreamSynchronize(s->st) != hipSuccess) r = fail(s, PIC_EDEVICE, "timing sync");
+    for (int k = 0; k < nsteps && !r; ++k) {
+        hipEvent_t* e = &ev[(size_t)5 * k];
         float a = 0.f, b = 0.f, c = 0.f;
-        (void)hipEventElapsedTime(&a, ev[0], ev[1]);
-        (void)hipEventElapsedTime(&b, ev[1], ev[2]);
+        (void)hipEventElapsedTime(&a, e[2], e[3]);
+        (void)hipEventElapsedTime(&b, e[3], e[4]);
         tp += a;
         tf += b;
-        if (sort) {
-            (void)hipEventElapsedTime(&c, ev[4], ev[5]);
+        if (sorted[k]) {
+            (void)hipEventElapsedTime(&c, e[0], e[1]);
             ts += c;
             ++nsort;
         }
-        s->step++;
     }
-    for (auto& e : ev) (void)hipEventDestroy(e);
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
     if (r) return r;
     out[0] = nsteps > 0 ? tp / nsteps : 0.0;
     out[1] = nsteps > 0 ? tf / nsteps : 0.0;
