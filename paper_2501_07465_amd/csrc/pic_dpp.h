@@ -68,6 +68,43 @@ __device__ __forceinline__ R seg_scan(R v, unsigned m)
     return v;
 }
 
+// Segmented inclusive scan of N values at once over the first STEPS DPP steps (STEPS <= 6: the
+// scan spans groups of 2^STEPS lanes).  Step k is applied to every value before step k + 1, so
+// the DPP reads of one value follow the writes of the others and need no wait states.
+template <int STEPS, int N, typename R>
+__device__ __forceinline__ void seg_scan_n(R (&v)[N], unsigned m)
+{
+    R t[N];
+#define PIC_SCAN_STEP(K, CTRL, ROWMASK)                                                \
+    if (STEPS > K) {                                                                   \
+        _Pragma("unroll") for (int q = 0; q < N; ++q) t[q] = dpp_r<CTRL, ROWMASK>(v[q]); \
+        _Pragma("unroll") for (int q = 0; q < N; ++q) if (m & (1u << K)) v[q] += t[q];  \
+    }
+    PIC_SCAN_STEP(0, kRowShr1, 0xf)
+    PIC_SCAN_STEP(1, kRowShr2, 0xf)
+    PIC_SCAN_STEP(2, kRowShr4, 0xf)
+    PIC_SCAN_STEP(3, kRowShr8, 0xf)
+    PIC_SCAN_STEP(4, kRowBcast15, 0xa)
+    PIC_SCAN_STEP(5, kRowBcast31, 0xc)
+#undef PIC_SCAN_STEP
+}
+
+// Step masks of seg_masks for the first STEPS steps only.
+template <int STEPS>
+__device__ __forceinline__ unsigned seg_masks_n(bool head)
+{
+    int f = head ? 1 : 0;
+    unsigned m = 0;
+    int fu;
+    if (STEPS > 0) { fu = dpp_i<kRowShr1, 0xf>(f);    if (!f) m |= 1u;  f |= fu; }
+    if (STEPS > 1) { fu = dpp_i<kRowShr2, 0xf>(f);    if (!f) m |= 2u;  f |= fu; }
+    if (STEPS > 2) { fu = dpp_i<kRowShr4, 0xf>(f);    if (!f) m |= 4u;  f |= fu; }
+    if (STEPS > 3) { fu = dpp_i<kRowShr8, 0xf>(f);    if (!f) m |= 8u;  f |= fu; }
+    if (STEPS > 4) { fu = dpp_i<kRowBcast15, 0xa>(f); if (!f) m |= 16u; f |= fu; }
+    if (STEPS > 5) { if (!f) m |= 32u; }
+    return m;
+}
+
 // Plain inclusive scan over the whole wavefront (one segment starting at lane 0).
 __device__ __forceinline__ unsigned scan_masks(int lane) { return seg_masks(lane == 0); }
 
