@@ -474,7 +474,8 @@ static size_t plan(pic_sim* s, char* base, bool assign)
         for (int c = 0; c < 3; ++c) h.E[k][c] = P.takeb(L * es);
         for (int c = 0; c < 3; ++c) h.B[k][c] = P.takeb(L * es);
     }
-    for (int p = 0; p < 2; ++p) h.jover[p] = P.takeb(3 * L * es);
+    for (int p = 0; p < 2; ++p) h.J[p] = P.takeb(3 * L * es);
+    h.fdirty = P.take<int>(2 * (size_t)h.nftiles);
     s->max_slots = count_slot_tiles(s);
     h.max_slots = s->max_slots;
     // units of a tile: ceil(c_t / U) <= c_t / U + 1, so all units <= ceil(N / U) + active tiles
@@ -485,7 +486,6 @@ static size_t plan(pic_sim* s, char* base, bool assign)
         max_units += (ntot + h.unit_cap - 1) / h.unit_cap;
     }
     h.max_units = (int)std::min<long long>(max_units, 1LL << 30);
-    h.slots = P.takeb((size_t)h.max_units * 3 * h.Vj * es);
     h.tile_slot = P.take<int>(h.ntiles);
     h.tile_nslot = P.take<int>(h.ntiles);
     h.active = P.take<int>(h.ntiles);

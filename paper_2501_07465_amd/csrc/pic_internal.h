@@ -91,19 +91,20 @@ struct SimDev {
     // fields, planar [comp][z][y][x], R; two buffers: step n reads [n & 1] and writes [(n+1) & 1]
     void* E[2][3];
     void* B[2][3];
-    void* slots;           // per work unit: [3][Vj] current window
-    int* tile_slot;        // [ntiles]: first unit (slot) of an active tile, -1 otherwise
-    int* tile_nslot;       // [ntiles]: units of an active tile (consecutive slots)
+    int* tile_slot;        // [ntiles]: first unit of an active tile, -1 otherwise
+    int* tile_nslot;       // [ntiles]: units of an active tile (consecutive)
     int* active;           // [ntiles]: active tile list
     int* n_active;         // device scalar
     int max_slots;         // capacity of the active list (tiles that can hold particles)
     int* units;            // [max_units][3]: tile, first and end particle in the tile's
                            // species-concatenated order
     int* n_units;          // device scalar
-    int max_units;         // capacity of the unit list and of the slot array
+    int max_units;         // capacity of the unit list
     int unit_cap;          // most particles per unit (0: one unit per tile)
     int* sort_hist;        // radix-sort digit histogram scratch
-    void* jover[2];        // [3][Lvol] current of particles outside their window (rare)
+    void* J[2];            // [3][Lvol] J^{n+1/2} by step parity: every tile window's current is
+                           // added by atomics, particles outside their window add directly
+    int* fdirty;           // [2][nftiles] field tiles whose owned nodes of J[p] hold deposits
     long long* over_stamp; // [2] step+1 of the last overflow per parity
     unsigned long long* over_count;
     double* partials;      // [max_units][3] per unit: sum q w v_{n+1/2}
