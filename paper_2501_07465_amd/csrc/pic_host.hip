@@ -186,7 +186,7 @@ static int setup_grid(pic_sim* s)
     }
     // packed cell layout
     const int sh[3][3] = {{0, 31, 31}, {0, 16, 31}, {0, 11, 22}};
-    const int mk[3][3] = {{0x7fffffff, 0, 0}, {0xffff, 0x7fff, 0}, {0x7ff, 0x7ff, 0x3ff}};
+    const int mk[3][3] = {{0x7fffffff, 0, 0}, {0xffff, 0xffff, 0}, {0x7ff, 0x7ff, 0x3ff}};
     for (int a = 0; a < 3; ++a) {
         h.pshift[a] = sh[g.dims - 1][a] >= 31 ? 0 : sh[g.dims - 1][a];
         h.pmask[a] = mk[g.dims - 1][a];

@@ -126,16 +126,19 @@ struct SimDev {
 };
 
 // ---- small host/device helpers ----------------------------------------------------------------
+// Packed cell: the fields fill all 32 bits (2D: 16 + 16, 3D: 11 + 11 + 10), so packing and
+// unpacking run on unsigned values; the stored int is only ever unpacked, never compared.
 __host__ __device__ inline int pack_cell(const SimDev& S, int i, int j, int k)
 {
-    return (i << S.pshift[0]) | (j << S.pshift[1]) | (k << S.pshift[2]);
+    return (int)(((unsigned)i << S.pshift[0]) | ((unsigned)j << S.pshift[1]) | ((unsigned)k << S.pshift[2]));
 }
 
 __host__ __device__ inline void unpack_cell(const SimDev& S, int c, int out[3])
 {
-    out[0] = (c >> S.pshift[0]) & S.pmask[0];
-    out[1] = (c >> S.pshift[1]) & S.pmask[1];
-    out[2] = (c >> S.pshift[2]) & S.pmask[2];
+    const unsigned u = (unsigned)c;
+    out[0] = (int)((u >> S.pshift[0]) & (unsigned)S.pmask[0]);
+    out[1] = (int)((u >> S.pshift[1]) & (unsigned)S.pmask[1]);
+    out[2] = (int)((u >> S.pshift[2]) & (unsigned)S.pmask[2]);
 }
 
 // Tile-major cell key: tile id, then the cell inside the tile (x fastest).

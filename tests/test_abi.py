@@ -90,3 +90,65 @@ def test_counts_match_oracle_loader(oracle):
             assert pic.pic_init_species(h, pic.species_desc(sp), 1) == sid
             assert pic.pic_species_count(h, sid) == ref.count(sid)
         pic.pic_destroy(h)
+
+
+def _grid(dims, n, tile, periodic=1, block=256, unit=0):
+    from paper_2501_07465_amd import pic, workloads as W
+    w = {"name": "limits", "dims": dims, "n": list(n), "dx": [1e-9] * 3, "dt": W.cfl_dt(1e-9, dims),
+         "periodic": [periodic] * 3, "tile": list(tile), "sort_every": 20, "species": [], "unit": unit}
+    return pic.grid_desc(w, "fp32", False, block, 64, unit)
+
+
+@pytest.mark.parametrize("dims,n,tile", [
+    (1, [1 << 20, 1, 1], [256, 1, 1]),
+    (2, [65535, 16, 1], [16, 8, 1]),
+    (2, [16, 65535, 1], [8, 16, 1]),
+    (3, [2047, 8, 8], [8, 4, 4]),
+    (3, [8, 2047, 8], [4, 8, 4]),
+    (3, [8, 8, 1023], [4, 4, 8]),
+])
+def test_largest_extents_accepted_and_one_more_rejected(dims, n, tile):
+    """Every axis takes its documented maximum (the packed cell index holds it) and refuses one more."""
+    from paper_2501_07465_amd import pic
+    h = pic.pic_create(_grid(dims, n, tile))
+    assert pic.pic_footprint(h) > 0
+    pic.pic_destroy(h)
+    if dims == 1:
+        return
+    big = int(np.argmax(n))
+    m = list(n)
+    m[big] += 1
+    with pytest.raises(pic.PicError) as e:
+        pic.pic_create(_grid(dims, m, tile))
+    assert e.value.code == pic.PIC_EINVAL
+
+
+def test_key_space_beyond_int32_rejected():
+    """2D 65535 x 65535 fits the packed index but not a 31-bit tile-major key."""
+    from paper_2501_07465_amd import pic
+    with pytest.raises(pic.PicError) as e:
+        pic.pic_create(_grid(2, [65535, 65535, 1], [16, 16, 1]))
+    assert e.value.code == pic.PIC_EINVAL
+    assert "key space" in str(e.value)
+
+
+@pytest.mark.parametrize("block,unit,ok", [(64, 0, True), (512, 64, True), (100, 0, False), (1024, 0, False),
+                                           (256, 10, False), (256, -1, False), (256, 4096, True)])
+def test_block_and_unit_validation(block, unit, ok):
+    from paper_2501_07465_amd import pic
+    g = _grid(2, [64, 64, 1], [16, 8, 1], block=block, unit=unit)
+    if ok:
+        pic.pic_destroy(pic.pic_create(g))
+        return
+    with pytest.raises(pic.PicError) as e:
+        pic.pic_create(g)
+    assert e.value.code == pic.PIC_EINVAL
+
+
+def test_periodic_axis_shorter_than_its_window_rejected():
+    """A periodic axis must be long enough that one wrap maps every window node into the grid."""
+    from paper_2501_07465_amd import pic
+    pic.pic_destroy(pic.pic_create(_grid(2, [4, 64, 1], [4, 8, 1])))
+    with pytest.raises(pic.PicError) as e:
+        pic.pic_create(_grid(2, [3, 64, 1], [4, 8, 1]))
+    assert e.value.code == pic.PIC_EINVAL
