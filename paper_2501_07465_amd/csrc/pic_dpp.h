@@ -89,6 +89,59 @@ __device__ __forceinline__ void seg_scan_n(R (&v)[N], unsigned m)
 #undef PIC_SCAN_STEP
 }
 
+// FP32 form of seg_scan_n, on groups of 16 lanes (one DPP row; STEPS <= 4), for the N = 5, 8 and
+// 12 deposit values of 1D, 2D and 3D: each step adds the row-shifted value times a per-lane 0/1
+// factor with one v_fmac_f32 that takes its first operand through DPP (v + 1 * t rounds as v + t;
+// v + 0 * t is v), in place of a shift, an add and a select.  Written as assembly because the
+// compiler does not fold a DPP move into an FMA.  Source lanes outside the row are disabled by the
+// row shift (no bound_ctrl), so those lanes keep v.  A VALU write followed by a DPP read of the same
+// register needs two wait states on this architecture and the compiler cannot see into the asm, so
+// each step is one asm statement that starts with s_nop 1 (nothing can be scheduled between the
+// wait and the reads), and the last step ends with one.
+#define PIC_FM(i, f, sh) "v_fmac_f32_dpp %" #i ", %" #i ", %" #f " row_shr:" #sh " row_mask:0xf bank_mask:0xf\n\t"
+#define PIC_FM5(f, sh) PIC_FM(0, f, sh) PIC_FM(1, f, sh) PIC_FM(2, f, sh) PIC_FM(3, f, sh) PIC_FM(4, f, sh)
+#define PIC_FM8(f, sh) PIC_FM5(f, sh) PIC_FM(5, f, sh) PIC_FM(6, f, sh) PIC_FM(7, f, sh)
+#define PIC_FM12(f, sh) PIC_FM8(f, sh) PIC_FM(8, f, sh) PIC_FM(9, f, sh) PIC_FM(10, f, sh) PIC_FM(11, f, sh)
+#define PIC_V5 "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4])
+#define PIC_V8 PIC_V5, "+v"(v[5]), "+v"(v[6]), "+v"(v[7])
+#define PIC_V12 PIC_V8, "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11])
+
+template <int N, int SH, bool LAST>
+__device__ __forceinline__ void fmac_step(float (&v)[N], float f)
+{
+    static_assert(N == 5 || N == 8 || N == 12, "deposit value counts of 1D, 2D, 3D");
+#define PIC_STEP_ASM(NN, sh)                                                                        \
+    if constexpr (N == NN && SH == sh) {                                                            \
+        if constexpr (LAST)                                                                         \
+            asm volatile("s_nop 1\n\t" PIC_FM##NN(NN, sh) "s_nop 1" : PIC_V##NN : "v"(f));          \
+        else                                                                                        \
+            asm volatile("s_nop 1\n\t" PIC_FM##NN(NN, sh) : PIC_V##NN : "v"(f));                    \
+    }
+    PIC_STEP_ASM(5, 1) PIC_STEP_ASM(5, 2) PIC_STEP_ASM(5, 4) PIC_STEP_ASM(5, 8)
+    PIC_STEP_ASM(8, 1) PIC_STEP_ASM(8, 2) PIC_STEP_ASM(8, 4) PIC_STEP_ASM(8, 8)
+    PIC_STEP_ASM(12, 1) PIC_STEP_ASM(12, 2) PIC_STEP_ASM(12, 4) PIC_STEP_ASM(12, 8)
+#undef PIC_STEP_ASM
+}
+#undef PIC_FM
+#undef PIC_FM5
+#undef PIC_FM8
+#undef PIC_FM12
+#undef PIC_V5
+#undef PIC_V8
+#undef PIC_V12
+
+template <int STEPS, int N>
+__device__ __forceinline__ void seg_scan_n(float (&v)[N], unsigned m)
+{
+    static_assert(STEPS >= 1 && STEPS <= 4, "row shifts only");
+    const float f0 = (m & 1u) ? 1.0f : 0.0f, f1 = (m & 2u) ? 1.0f : 0.0f;
+    const float f2 = (m & 4u) ? 1.0f : 0.0f, f3 = (m & 8u) ? 1.0f : 0.0f;
+    fmac_step<N, 1, STEPS == 1>(v, f0);
+    if constexpr (STEPS > 1) fmac_step<N, 2, STEPS == 2>(v, f1);
+    if constexpr (STEPS > 2) fmac_step<N, 4, STEPS == 3>(v, f2);
+    if constexpr (STEPS > 3) fmac_step<N, 8, true>(v, f3);
+}
+
 // Step masks of seg_masks for the first STEPS steps only.
 template <int STEPS>
 __device__ __forceinline__ unsigned seg_masks_n(bool head)
