@@ -509,6 +509,7 @@ static size_t plan(pic_sim* s, char* base, bool assign)
     long long nb = 1;
     for (auto& x : s->sp) nb = std::max(nb, (x.n + sort_ipb(x.n) - 1) / sort_ipb(x.n));
     h.sort_hist = P.take<int>((size_t)256 * nb);
+    h.sort_part = P.take<int>(256);
     h.nspecies = (int)s->sp.size();
     for (size_t i = 0; i < s->sp.size(); ++i) {
         SpeciesHost& x = s->sp[i];
@@ -794,7 +795,7 @@ static int enqueue_sort_all(pic_sim* s, std::vector<int>* sorted)
             HIPCHK(s, enqueue_sort(s->d, (int)i, (int)x.n, s->passes, s->es, s->st));
             x.parity ^= 1;
         }
-        HIPCHK(s, enqueue_ranges(s->d, (int)i, s->h.ntiles, s->passes, s->st));
+        HIPCHK(s, enqueue_ranges(s->d, (int)i, s->h.ntiles, s->passes, x.n > 0, s->st));
         x.sorted_once = true;
         if (sorted) sorted->push_back((int)i);
     }

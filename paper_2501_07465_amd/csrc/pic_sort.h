@@ -13,11 +13,12 @@ inline int sort_ipb(long long n)
     return (int)ipb;
 }
 
-// Stable radix sort of species s by cell key (passes of 8 bits), permutation of its arrays
-// into the alternates and pointer swap.  elem = 4 (FP32 form) or 8 (FP64 form).
+// Stable radix sort of species s by cell key (passes of 8 bits) and permutation of its arrays
+// into the alternates.  elem = 4 (FP32 form) or 8 (FP64 form).  enqueue_ranges with swap = true
+// must follow: it swaps the arrays with their alternates.
 hipError_t enqueue_sort(SimDev* dS, int s, int n, int passes, int elem, hipStream_t st);
-// Per-tile particle ranges of species s from its sorted keys.
-hipError_t enqueue_ranges(SimDev* dS, int s, int ntiles, int passes, hipStream_t st);
+// Per-tile particle ranges of species s from its sorted keys; after a sort of s, swap = true.
+hipError_t enqueue_ranges(SimDev* dS, int s, int ntiles, int passes, bool swap, hipStream_t st);
 // Keys of species s into its key buffer (diagnostics).
 hipError_t enqueue_keys_only(SimDev* dS, int s, int n, hipStream_t st);
 // Active tile list and slots.

@@ -49,56 +49,67 @@ __global__ void __launch_bounds__(kSortBlock) k_radix_hist(SimDev* __restrict__ 
         for (int d = threadIdx.x; d < kRadix; d += blockDim.x) S->sort_hist[d * nb + b] = h[d];
 }
 
-// exclusive scan of hist[0 .. kRadix * nb) by one block.  Wave w owns a contiguous segment; its
-// lanes read it 64 consecutive entries at a time (coalesced), kScanGroup rows in flight.  Pass 1
-// sums each segment, pass 2 scans it row by row (DPP wavefront scan) with the segment's offset
-// carried in.
+// Exclusive scan of hist[0 .. kRadix * nb) (digit-major) in two kernels with one block per digit:
+// the row sums, then each row scanned with its offset (the sum of the rows of lower digits).
 constexpr int kScanThreads = 1024;
-constexpr int kScanGroup = 16;
 
-__global__ void __launch_bounds__(kScanThreads) k_radix_scan(SimDev* __restrict__ S, int s, int ipb)
+// inclusive scan of v over the block (kScanThreads threads): DPP wavefront scans, then the wave
+// totals in order; *total receives the block total
+__device__ __forceinline__ int block_scan(int v, int* wsum, int* total)
 {
     constexpr int NW = kScanThreads / 64;
-    __shared__ int wsum[NW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int inc = seg_scan<int>(v, scan_masks(lane));
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    int carry = 0, all = 0;
+    for (int w = 0; w < NW; ++w) {
+        const int x = wsum[w];
+        if (w < wave) carry += x;
+        all += x;
+    }
+    __syncthreads();
+    *total = all;
+    return carry + inc;
+}
+
+// part[d] = sum over blocks b of hist[d * nb + b]
+__global__ void __launch_bounds__(kScanThreads) k_radix_rowsum(SimDev* __restrict__ S, int s, int ipb)
+{
+    __shared__ int wsum[kScanThreads / 64];
     const int n = S->sp[s].n;
     const int nb = (n + ipb - 1) / ipb;
-    const int total = kRadix * nb;
-    int* H = S->sort_hist;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int per_w = (total + NW * 64 - 1) / (NW * 64) * 64;
-    const int w0 = min(total, wave * per_w), w1 = min(total, w0 + per_w);
+    const int* row = S->sort_hist + (long long)blockIdx.x * nb;
     int acc = 0;
-    for (int g = w0; g < w1; g += 64 * kScanGroup) {
-        int v[kScanGroup];
-#pragma unroll
-        for (int k = 0; k < kScanGroup; ++k) {
-            const int i = g + k * 64 + lane;
-            v[k] = i < w1 ? H[i] : 0;
-        }
-#pragma unroll
-        for (int k = 0; k < kScanGroup; ++k) acc += v[k];
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) wsum[wave] = acc;
-    __syncthreads();
-    int carry = 0;
-    for (int w = 0; w < wave; ++w) carry += wsum[w];
-    const unsigned msk = scan_masks(lane);
-    for (int g = w0; g < w1; g += 64 * kScanGroup) {
-        int v[kScanGroup];
-#pragma unroll
-        for (int k = 0; k < kScanGroup; ++k) {
-            const int i = g + k * 64 + lane;
-            v[k] = i < w1 ? H[i] : 0;
-        }
-#pragma unroll
-        for (int k = 0; k < kScanGroup; ++k) {
-            const int inc = seg_scan<int>(v[k], msk);
-            const int i = g + k * 64 + lane;
-            if (i < w1) H[i] = carry + inc - v[k];
-            carry += __builtin_amdgcn_readlane(inc, 63);
-        }
+    for (int b = threadIdx.x; b < nb; b += kScanThreads) acc += row[b];
+    int total;
+    block_scan(acc, wsum, &total);
+    if (threadIdx.x == 0) S->sort_part[blockIdx.x] = total;
+}
+
+// row d of hist replaced by its exclusive prefix in the digit-major order: thread t scans its
+// run of k consecutive entries serially, the runs are combined by one block scan
+__global__ void __launch_bounds__(kScanThreads) k_radix_rowscan(SimDev* __restrict__ S, int s, int ipb)
+{
+    __shared__ int wsum[kScanThreads / 64];
+    const int n = S->sp[s].n;
+    const int nb = (n + ipb - 1) / ipb;
+    const int d = blockIdx.x, tid = threadIdx.x;
+    int total;
+    const int below = block_scan(tid < d ? S->sort_part[tid] : 0, wsum, &total);
+    (void)below;
+    const int offset = total;  // sum of the totals of digits 0 .. d-1
+    int* row = S->sort_hist + (long long)d * nb;
+    const int k = (nb + kScanThreads - 1) / kScanThreads;
+    const int b0 = min(nb, tid * k), b1 = min(nb, b0 + k);
+    int run = 0;
+    for (int b = b0; b < b1; ++b) run += row[b];
+    const int inc = block_scan(run, wsum, &total);
+    int acc = offset + inc - run;
+    for (int b = b0; b < b1; ++b) {
+        const int x = row[b];
+        row[b] = acc;
+        acc += x;
     }
 }
 
@@ -196,22 +207,20 @@ __global__ void k_permute(SimDev* __restrict__ S, int s, int passes, int elem)
     }
 }
 
-// Swap the particle arrays with their alternates (one thread).
-__global__ void k_swap(SimDev* __restrict__ S, int s)
+// tile_start[t] = first sorted index whose key >= t * tile volume (lower bound), t = 0..ntiles.
+// After a sort (swap != 0) the first thread also swaps the particle arrays with their alternates,
+// into which the permutation was gathered; nothing here reads them.
+__global__ void k_tile_ranges(SimDev* __restrict__ S, int s, int passes, int swap)
 {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    SpeciesDev& sp = S->sp[s];
-    int* c = sp.cell; sp.cell = sp.cell_alt; sp.cell_alt = c;
-    for (int a = 0; a < 3; ++a) {
-        void* t = sp.off[a]; sp.off[a] = sp.off_alt[a]; sp.off_alt[a] = t;
-        t = sp.v[a]; sp.v[a] = sp.v_alt[a]; sp.v_alt[a] = t;
-        t = sp.xi[a]; sp.xi[a] = sp.xi_alt[a]; sp.xi_alt[a] = t;
+    if (swap && blockIdx.x == 0 && threadIdx.x == 0) {
+        SpeciesDev& w = S->sp[s];
+        int* c = w.cell; w.cell = w.cell_alt; w.cell_alt = c;
+        for (int a = 0; a < 3; ++a) {
+            void* t = w.off[a]; w.off[a] = w.off_alt[a]; w.off_alt[a] = t;
+            t = w.v[a]; w.v[a] = w.v_alt[a]; w.v_alt[a] = t;
+            t = w.xi[a]; w.xi[a] = w.xi_alt[a]; w.xi_alt[a] = t;
+        }
     }
-}
-
-// tile_start[t] = first sorted index whose key >= t * tile volume (lower bound), t = 0..ntiles
-__global__ void k_tile_ranges(SimDev* __restrict__ S, int s, int passes)
-{
     const SpeciesDev& sp = S->sp[s];
     const int* keys = (passes & 1) ? sp.keys_alt : sp.keys;
     const int n = sp.n;
@@ -230,63 +239,83 @@ __global__ void k_tile_ranges(SimDev* __restrict__ S, int s, int passes)
 // Active tiles (any species has particles) in tile order, and their work units: a tile holding
 // c particles (all species) gets ceil(c / U) units of at most U particles, in its species-
 // concatenated order (one unit when U is 0); the units of a tile take consecutive slots.
-__global__ void __launch_bounds__(1024) k_compact(SimDev* __restrict__ S)
+// One block, rounds of kCompactK * 1024 tiles (each thread kCompactK consecutive tiles): a first
+// sweep forms the totals (whether the lists fit), a second places the tiles and units of each
+// round with block scans.
+constexpr int kCompactK = 4;
+
+__global__ void __launch_bounds__(kScanThreads) k_compact(SimDev* __restrict__ S)
 {
-    __shared__ int wa[16], wu[16];
+    __shared__ int wsum[kScanThreads / 64];
     const int nt = S->ntiles;
     const int U = S->unit_cap;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-    const int per = (nt + blockDim.x - 1) / blockDim.x;
-    const int lo = min(nt, tid * per), hi = min(nt, lo + per);
+    const int tid = threadIdx.x;
+    constexpr int R = kCompactK * kScanThreads;
     auto count = [&](int t) {
         int c = 0;
         for (int s = 0; s < S->nspecies; ++s) c += S->sp[s].tile_start[t + 1] - S->sp[s].tile_start[t];
         return c;
     };
     auto nunits = [&](int c) { return c == 0 ? 0 : (U > 0 ? (c + U - 1) / U : 1); };
+    // totals
     int ca = 0, cu = 0;
-    for (int t = lo; t < hi; ++t) {
-        const int c = count(t);
-        ca += c > 0 ? 1 : 0;
-        cu += nunits(c);
+    for (int base = 0; base < nt; base += R) {
+        int c[kCompactK];
+#pragma unroll
+        for (int j = 0; j < kCompactK; ++j) {
+            const int t = base + tid * kCompactK + j;
+            c[j] = t < nt ? count(t) : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kCompactK; ++j) {
+            ca += c[j] > 0 ? 1 : 0;
+            cu += nunits(c[j]);
+        }
     }
-    // exclusive prefixes of the active-tile and unit counts over threads
-    int ia = ca, iu = cu;
-    for (int off = 1; off < 64; off <<= 1) {
-        const int ta = __shfl_up(ia, off, 64), tu = __shfl_up(iu, off, 64);
-        if (lane >= off) { ia += ta; iu += tu; }
-    }
-    if (lane == 63) { wa[wave] = ia; wu[wave] = iu; }
-    __syncthreads();
-    int ba = 0, bu = 0, ta = 0, tu = 0;
-    for (int w = 0; w < nw; ++w) {
-        if (w < wave) { ba += wa[w]; bu += wu[w]; }
-        ta += wa[w];
-        tu += wu[w];
-    }
+    int ta, tu;
+    block_scan(ca, wsum, &ta);
+    block_scan(cu, wsum, &tu);
     // a list that does not fit (particles in tiles the capacity did not count) is dropped whole
     // and flagged: no particle moves this period
     const bool fits = ta <= S->max_slots && tu <= S->max_units;
-    int ra = ba + ia - ca, ru = bu + iu - cu;
-    for (int t = lo; t < hi; ++t) {
-        const int c = count(t);
-        if (c > 0 && fits) {
-            const int k = nunits(c);
-            S->active[ra] = t;
-            S->tile_slot[t] = ru;
-            S->tile_nslot[t] = k;
-            for (int j = 0; j < k; ++j) {
-                int* u = S->units + 3 * (ru + j);
-                u[0] = t;
-                u[1] = U > 0 ? j * U : 0;
-                u[2] = U > 0 ? min(c, (j + 1) * U) : c;
-            }
-            ++ra;
-            ru += k;
-        } else {
-            S->tile_slot[t] = -1;
-            S->tile_nslot[t] = 0;
+    int oa = 0, ou = 0;  // active tiles and units of the rounds before
+    for (int base = 0; base < nt; base += R) {
+        int c[kCompactK];
+        int ra = 0, ru = 0;
+#pragma unroll
+        for (int j = 0; j < kCompactK; ++j) {
+            const int t = base + tid * kCompactK + j;
+            c[j] = t < nt ? count(t) : 0;
+            ra += c[j] > 0 ? 1 : 0;
+            ru += nunits(c[j]);
         }
+        int sa, su;
+        int pa = block_scan(ra, wsum, &sa) - ra + oa;
+        int pu = block_scan(ru, wsum, &su) - ru + ou;
+#pragma unroll
+        for (int j = 0; j < kCompactK; ++j) {
+            const int t = base + tid * kCompactK + j;
+            if (t >= nt) continue;
+            if (c[j] > 0 && fits) {
+                const int k = nunits(c[j]);
+                S->active[pa] = t;
+                S->tile_slot[t] = pu;
+                S->tile_nslot[t] = k;
+                for (int q = 0; q < k; ++q) {
+                    int* u = S->units + 3 * (pu + q);
+                    u[0] = t;
+                    u[1] = U > 0 ? q * U : 0;
+                    u[2] = U > 0 ? min(c[j], (q + 1) * U) : c[j];
+                }
+                ++pa;
+                pu += k;
+            } else {
+                S->tile_slot[t] = -1;
+                S->tile_nslot[t] = 0;
+            }
+        }
+        oa += sa;
+        ou += su;
     }
     if (tid == 0) {
         *S->n_active = fits ? ta : 0;
@@ -305,11 +334,11 @@ hipError_t enqueue_sort(SimDev* dS, int s, int n, int passes, int elem, hipStrea
         hipLaunchKernelGGL(k_keys, dim3(g > 0 ? g : 1), dim3(256), 0, st, dS, s);
         for (int p = 0; p < passes; ++p) {
             hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortBlock), 0, st, dS, s, p, ipb);
-            hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(kScanThreads), 0, st, dS, s, ipb);
+            hipLaunchKernelGGL(k_radix_rowsum, dim3(kRadix), dim3(kScanThreads), 0, st, dS, s, ipb);
+            hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(kScanThreads), 0, st, dS, s, ipb);
             hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortBlock), 0, st, dS, s, p, ipb);
         }
         hipLaunchKernelGGL(k_permute, dim3(g > 0 ? g : 1), dim3(256), 0, st, dS, s, passes, elem);
-        hipLaunchKernelGGL(k_swap, dim3(1), dim3(64), 0, st, dS, s);
     }
     return hipGetLastError();
 }
@@ -321,10 +350,10 @@ hipError_t enqueue_keys_only(SimDev* dS, int s, int n, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t enqueue_ranges(SimDev* dS, int s, int ntiles, int passes, hipStream_t st)
+hipError_t enqueue_ranges(SimDev* dS, int s, int ntiles, int passes, bool swap, hipStream_t st)
 {
     const int g = (ntiles + 1 + 255) / 256;
-    hipLaunchKernelGGL(k_tile_ranges, dim3(g), dim3(256), 0, st, dS, s, passes);
+    hipLaunchKernelGGL(k_tile_ranges, dim3(g), dim3(256), 0, st, dS, s, passes, swap ? 1 : 0);
     return hipGetLastError();
 }
 
