@@ -65,6 +65,22 @@ def test_fp64_matches_oracle_from_same_state(oracle, name, steps):
     assert _rel(sg, sr) < 1e-12
 
 
+@pytest.mark.parametrize("periodic", [[0, 0, 1], [1, 1, 1]])
+def test_fp64_2d_all_open_and_all_periodic(oracle, periodic):
+    """The small disk with both in-plane axes open (Mur on every face and corner, source plane
+    ending on open faces) or both periodic, FP64 GPU vs oracle over 60 steps."""
+    from paper_2501_07465_amd import pic
+    w = _small("disk2d")
+    w["periodic"] = list(periodic)
+    w["source"]["index"] = [6, 0, 0]
+    print(f"case fp64 disk periodic {periodic}", flush=True)
+    ref = oracle.build_workload(w)
+    sim = pic.Simulation(w, precision="fp64", states=ref.state(), fields=ref.fields(), graphs=False)
+    sim.step(60)
+    ref.step(60)
+    _compare(sim, ref, w, 1e-12, f"fp64 disk periodic {periodic}")
+
+
 def test_fp64_slab_1000_steps(oracle):
     """The 1D slab at full size (256 cells, 64 ppc) for 1000 steps, FP64 GPU vs oracle."""
     from paper_2501_07465_amd import pic, workloads as W
