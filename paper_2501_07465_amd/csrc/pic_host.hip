@@ -219,7 +219,7 @@ static int setup_grid(pic_sim* s)
     {
         int ve = 1, vb = 1, vj = 1;
         for (int a = 0; a < g.dims; ++a) { ve *= h.FT[a] + 3; vb *= h.FT[a] + 2; vj *= h.FT[a] + 1; }
-        fl = g.dims == 2 ? 0 : 3 * (ve + vb + 2 * vj);  // the 2D row sweep keeps its rows in registers
+        fl = g.dims == 2 ? 0 : 3 * (ve + vb + vj);  // E_n, B, J (E_{n+1} overwrites J); the 2D row sweep uses none
     }
     s->field_lds = fl;
     h.dt = g.dt;

@@ -42,7 +42,7 @@ struct FieldTile<1> { static constexpr int X = 256, Y = 1, Z = 1; };
 template <>
 struct FieldTile<2> { static constexpr int X = 61, Y = 6, Z = 1; };  // row-sweep task: 61 columns of a wavefront, 6 rows
 template <>
-struct FieldTile<3> { static constexpr int X = 16, Y = 4, Z = 4; };
+struct FieldTile<3> { static constexpr int X = 16, Y = 8, Z = 4; };
 
 constexpr int kGL = 2;       // low-side halo of both windows
 constexpr int kGHf = 2;      // high-side halo of the field window
