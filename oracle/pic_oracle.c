@@ -412,6 +412,7 @@ struct or_sim {
     double* E[3];
     double* B[3];
     double* J[3];    /* particle current of the last step, J^{n+1/2}         */
+    double* einv[3]; /* inverse permittivity at the E_c nodes (NULL: unit)   */
     double* rho_ion; /* fixed background charge density at nodes            */
     int have_ion;
     int nsp;
@@ -502,7 +503,7 @@ int or_create(const or_grid* g, or_sim** out)
 void or_destroy(or_sim* s)
 {
     if (!s) return;
-    for (int c = 0; c < 3; ++c) { free(s->E[c]); free(s->B[c]); free(s->J[c]); }
+    for (int c = 0; c < 3; ++c) { free(s->E[c]); free(s->B[c]); free(s->J[c]); free(s->einv[c]); }
     free(s->rho_ion);
     for (int i = 0; i < s->nsp; ++i) { free(s->sp[i].C); free(s->sp[i].O); free(s->sp[i].v); free(s->sp[i].xi); }
     free(s->series);
@@ -1080,7 +1081,10 @@ static void e_step(or_sim* s, double t_half)
                     if (mur_axis(s, c, ijk) >= 0) continue;
                     double curl = dbwd(s, s->B[a2], i, j, k, a1) - dbwd(s, s->B[a1], i, j, k, a2);
                     double jc = s->J[c][fidx(s, i, j, k)] + (source_hits(s, c, ijk) ? jsrc : 0.0);
-                    s->E[c][fidx(s, i, j, k)] += dt * (c2 * curl - jc / EPS0);
+                    /* eq:consteps: the curl and current terms are scaled by the inverse
+                     * dielectric tensor, here diagonal and taken at the E_c node */
+                    double ei = s->einv[c] ? s->einv[c][fidx(s, i, j, k)] : 1.0;
+                    s->E[c][fidx(s, i, j, k)] += dt * ei * (c2 * curl - jc / EPS0);
                 }
     }
     for (int c = 0; c < 3; ++c) {
@@ -1090,7 +1094,9 @@ static void e_step(or_sim* s, double t_half)
     /* Mur (1981), first order: E^{n+1}_b = E^n_{b'} + k (E^{n+1}_{b'} - E^n_b),
      * b' the inward neighbour, k = (c dt - dx) / (c dt + dx).  The inward
      * value is the one after the curl update (at an edge, where the inward
-     * neighbour is itself on a face, that is its old value). */
+     * neighbour is itself on a face, that is its old value).
+     * Reading: the faces absorb at the vacuum speed c; the inverse permittivity
+     * is not used on face nodes (media end before the open faces). */
     for (int c = 0; c < 3; ++c) {
         int half[3];
         stag_E(c, half);
@@ -1258,6 +1264,22 @@ int or_set_fields(or_sim* s, const double* e, const double* b)
     return 0;
 }
 
+int or_set_eps_inv(or_sim* s, const double* einv)
+{
+    if (einv)
+        for (size_t q = 0; q < 3 * s->len; ++q)
+            if (!(einv[q] > 0.0) || !isfinite(einv[q])) return -1;
+    for (int c = 0; c < 3; ++c) {
+        free(s->einv[c]);
+        s->einv[c] = NULL;
+        if (!einv) continue;
+        s->einv[c] = (double*)malloc(sizeof(double) * s->len);
+        if (!s->einv[c]) return -2;
+        memcpy(s->einv[c], einv + c * s->len, sizeof(double) * s->len);
+    }
+    return 0;
+}
+
 int or_get_current(const or_sim* s, double* j)
 {
     for (int c = 0; c < 3; ++c) memcpy(j + c * s->len, s->J[c], sizeof(double) * s->len);
@@ -1281,7 +1303,8 @@ int or_set_ion_background(or_sim* s, int uniform)
 }
 
 /* 1D periodic: E_x from the discrete Gauss law over rho_e + rho_ion,
- * E_x(i+1/2) = E_x(i-1/2) + dx rho_i / eps0, with zero mean. */
+ * D_x(i+1/2) = D_x(i-1/2) + dx rho_i / eps0 with D_x / eps0 = eps E_x of zero
+ * mean, then E_x = einv D_x / eps0 (E_x itself for the unit tensor). */
 int or_gauss_init_1d(or_sim* s)
 {
     if (s->g.dims != 1 || !s->g.periodic[0] || !s->have_ion) return -1;
@@ -1298,7 +1321,10 @@ int or_gauss_init_1d(or_sim* s)
     }
     for (long i = 0; i < n; ++i) mean += s->E[0][i];
     mean /= (double)n;
-    for (long i = 0; i < n; ++i) s->E[0][i] -= mean;
+    for (long i = 0; i < n; ++i) {
+        s->E[0][i] -= mean;
+        if (s->einv[0]) s->E[0][i] *= s->einv[0][i];
+    }
     free(rho);
     return 0;
 }
@@ -1313,8 +1339,10 @@ double or_field_energy(const or_sim* s)
         for (long k = 0; k < valid_len(s, 2, hE[2]); ++k)
             for (long j = 0; j < valid_len(s, 1, hE[1]); ++j)
                 for (long i = 0; i < valid_len(s, 0, hE[0]); ++i) {
-                    double e = s->E[c][fidx(s, i, j, k)];
-                    u += 0.5 * EPS0 * e * e * dv;
+                    /* electric energy density eps0 eps E^2 / 2 (eps = 1 / einv) */
+                    size_t q = fidx(s, i, j, k);
+                    double e = s->E[c][q];
+                    u += 0.5 * EPS0 * e * e * dv / (s->einv[c] ? s->einv[c][q] : 1.0);
                 }
         for (long k = 0; k < valid_len(s, 2, hB[2]); ++k)
             for (long j = 0; j < valid_len(s, 1, hB[1]); ++j)
@@ -1338,11 +1366,18 @@ double or_kinetic_energy(const or_sim* s, int sid)
     return e;
 }
 
-/* max over interior nodes of |div E - (rho_e + rho_ion) / eps0|. */
+/* max over interior nodes of |div D / eps0 - (rho_e + rho_ion) / eps0| with
+ * D / eps0 = eps E (eps = 1 / einv per component; E itself for the unit tensor). */
 double or_gauss_residual(const or_sim* s, double* scale)
 {
     double* rho = (double*)malloc(sizeof(double) * s->len);
+    double* D[3] = {NULL, NULL, NULL};
     if (!rho) return NAN;
+    for (int c = 0; c < 3; ++c) {
+        D[c] = (double*)malloc(sizeof(double) * s->len);
+        if (!D[c]) { for (int d = 0; d < c; ++d) free(D[d]); free(rho); return NAN; }
+        for (size_t q = 0; q < s->len; ++q) D[c][q] = s->einv[c] ? s->E[c][q] / s->einv[c][q] : s->E[c][q];
+    }
     deposit_rho(s, rho);
     double res = 0.0, sc = 0.0;
     for (long k = 0; k < valid_len(s, 2, 0); ++k)
@@ -1354,12 +1389,13 @@ double or_gauss_residual(const or_sim* s, double* scale)
                     if (is_open(s, a) && (ijk[a] == 0 || ijk[a] == s->g.n[a])) interior = 0;
                 if (!interior) continue;
                 size_t q = fidx(s, i, j, k);
-                double div = dbwd(s, s->E[0], i, j, k, 0) + dbwd(s, s->E[1], i, j, k, 1) +
-                             dbwd(s, s->E[2], i, j, k, 2);
+                double div = dbwd(s, D[0], i, j, k, 0) + dbwd(s, D[1], i, j, k, 1) +
+                             dbwd(s, D[2], i, j, k, 2);
                 double r = fabs(div - (rho[q] + (s->have_ion ? s->rho_ion[q] : 0.0)) / EPS0);
                 if (r > res) res = r;
                 if (fabs(rho[q]) / EPS0 > sc) sc = fabs(rho[q]) / EPS0;
             }
+    for (int c = 0; c < 3; ++c) free(D[c]);
     free(rho);
     if (scale) *scale = sc;
     return res;

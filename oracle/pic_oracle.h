@@ -118,6 +118,10 @@ int  or_keys(const or_sim* s, int sid, int32_t* keys);
 size_t or_field_len(const or_sim* s);
 void or_field_shape(const or_sim* s, int L[3]);
 int  or_get_fields(const or_sim* s, double* e, double* b);   /* [3][L] each */
+/* Sec. 4, eq:consteps with a diagonal, spatially varying dielectric tensor:
+ * einv[3][L] holds the inverse permittivity of component c at the E_c node
+ * (NULL restores the unit tensor).  Entries must be finite and positive. */
+int  or_set_eps_inv(or_sim* s, const double* einv);
 int  or_set_fields(or_sim* s, const double* e, const double* b);
 int  or_get_current(const or_sim* s, double* j);             /* last particle J, [3][L] */
 int  or_get_rho(const or_sim* s, double* rho);               /* particle rho at nodes, [L] */

@@ -188,6 +188,51 @@ def stream(n_requests=512, rate_hz=None, seed=7, scale=1.0):
     return reqs
 
 
+def with_dielectric(w: dict, eps, region=None) -> dict:
+    """A copy of workload w with a constant background permittivity eps = [eps_x, eps_y, eps_z]
+    (diagonal) inside region (default: the region of the first species), vacuum elsewhere."""
+    w = copy.deepcopy(w)
+    w["dielectric"] = {"eps": [float(e) for e in eps],
+                       "region": copy.deepcopy(region or w["species"][0]["region"])}
+    w["name"] = w["name"] + "_eps"
+    return w
+
+
+def field_extent(w: dict):
+    """Array extent per axis of a field component: n on periodic and inactive axes, n + 1 on open ones."""
+    return [w["n"][a] + (1 if a < w["dims"] and not w["periodic"][a] else 0) for a in range(3)]
+
+
+def eps_inv_map(w: dict):
+    """Inverse permittivity per E component at its Yee node ([3][L2][L1][L0]): 1/eps_c where the node
+    (half-integer along c, integer along the other active axes, in cell units) lies in the dielectric
+    region, 1 elsewhere.  None when the workload has no dielectric."""
+    d = w.get("dielectric")
+    if d is None:
+        return None
+    L = field_extent(w)
+    dims = w["dims"]
+    kk, jj, ii = np.meshgrid(np.arange(L[2], dtype=float), np.arange(L[1], dtype=float),
+                             np.arange(L[0], dtype=float), indexing="ij")
+    out = np.ones((3, L[2], L[1], L[0]))
+    reg = d["region"]
+    for c in range(3):
+        pos = [ii.copy(), jj.copy(), kk.copy()]
+        if c < dims:
+            pos[c] += 0.5
+        if reg["kind"] == "ball":
+            r2 = sum((pos[a] - reg["center"][a]) ** 2 for a in range(dims))
+            inside = r2 <= reg["radius"] ** 2
+        elif reg["kind"] == "box":
+            inside = np.ones_like(ii, dtype=bool)
+            for a in range(dims):
+                inside &= (pos[a] >= reg["lo"][a]) & (pos[a] < reg["hi"][a])
+        else:
+            inside = np.ones_like(ii, dtype=bool)
+        out[c][inside] = 1.0 / d["eps"][c]
+    return out
+
+
 WORKLOADS = {"slab1d": slab1d, "disk2d": disk2d, "sphere3d": sphere3d, "sheet2d": sheet2d}
 
 
