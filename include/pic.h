@@ -8,7 +8,8 @@
  *   bound (eq:modborisscheme2) and Dirac (Sec. 5) particles to v_{n+1/2},
  *   x_{n+1}; reflect at material boundaries (Sec. 3); deposit the current
  *   J^{n+1/2} (charge conserving); advance B by half a step, E by a step
- *   (eq:consteps with a unit dielectric tensor), B by half a step.
+ *   (eq:consteps with a unit or per-cell diagonal dielectric tensor), B by half
+ *   a step.
  *
  * Conventions for every call:
  *   - Return value: PIC_OK (0) or a negative PIC_E* code; the text of the last
@@ -79,6 +80,9 @@ typedef struct {
     double src_j0;      /* [A/m^2] */
     double src_omega;   /* [rad/s] */
     double src_tau;     /* [s]     */
+    int eps_cells;      /* 1: a per-cell diagonal inverse permittivity (eq:consteps) scales  */
+                        /* the E update; set by pic_load_eps_inv, unit until then.           */
+                        /* 0: the unit tensor (no arena space, no extra reads)               */
 } pic_grid_desc;
 
 /* A species.  Free carriers follow eq:tradlorentz, bound ones eq:modlorentz
@@ -148,6 +152,19 @@ int pic_load_particles(pic_sim* s, int sid, const double* x, const double* v,
 /* Copy fields in: e[3][L] and b[3][L] FP64 (B at integer time), where L is the
  * array extent of pic_field_shape().  Either may be NULL.  Synchronous. */
 int pic_load_fields(pic_sim* s, const double* e, const double* b);
+
+/* Sec. 4, eq:consteps: set the spatially varying dielectric tensor, diagonal,
+ * as its inverse einv[3][L] (FP64, L the extent of pic_field_shape): entry
+ * [c][k][j][i] scales the curl and current terms of the update of E_c at that
+ * node, E_c += dt einv (c^2 (curl B)_c - J_c / eps0).  The field energy uses
+ * eps0 E^2 / (2 einv) and the Gauss residual div(E / einv).  Open faces keep
+ * the vacuum Mur update (their entries are not used), so media should end
+ * before them.  Needs eps_cells = 1; until this call the tensor is the unit
+ * one.  Entries must be finite and positive, and dt must stay below the
+ * stability limit with the fastest light speed c sqrt(max einv).
+ * Synchronous.  Errors: PIC_EINVAL (eps_cells = 0, null or bad entries),
+ * PIC_ECFL, PIC_ESTATE (not bound, or in a batch), PIC_EDEVICE. */
+int pic_load_eps_inv(pic_sim* s, const double* einv);
 
 /* Array extent per axis of every field component: n for periodic (and
  * inactive) axes, n + 1 for open axes.  Component c of E sits at a half-integer

@@ -70,6 +70,7 @@ struct pic_sim {
     double* cont = nullptr;  // last continuity residual [2]
     int batch_refs = 0;      // member of a batch
     SimDev* d_batch = nullptr;  // the member's entry in the batch table
+    double einv_max = 1.0;   // largest loaded inverse permittivity (1 for the unit tensor)
 };
 
 // The device table the kernels of this simulation must read: its own, or its batch entry.
@@ -146,6 +147,7 @@ static int setup_grid(pic_sim* s)
         return fail(s, PIC_EINVAL, "block must be 64, 128, 256 or 512");
     if (g.series_cap <= 0) g.series_cap = 8192;
     if (g.unit < 0 || (g.unit > 0 && g.unit < 64)) return fail(s, PIC_EINVAL, "unit must be 0 or >= 64");
+    if (g.eps_cells != 0 && g.eps_cells != 1) return fail(s, PIC_EINVAL, "eps_cells must be 0 or 1");
     memset(&h, 0, sizeof(h));
     h.unit_cap = g.unit;
     h.dims = g.dims;
@@ -291,6 +293,29 @@ static void species_freqs(const SpeciesHost& x, double& wp2, double& wb2)
         for (int a = 0; a < 3; ++a) wb2 = std::max(wb2, x.d.omega0[a] * x.d.omega0[a]);
 }
 
+// eq:dtlimit with all declared species (plasma frequencies add, largest resonance) and, if given,
+// one more.  A dielectric scales the curl and current terms of the E update by einv, so the light
+// speed squared and the plasma frequencies squared take the factor max(1, largest einv).
+static int check_dt(pic_sim* s, const SpeciesHost* extra, double einv_max)
+{
+    double wp2 = 0.0, wb2 = 0.0;
+    std::vector<const SpeciesHost*> all;
+    for (auto& y : s->sp) all.push_back(&y);
+    if (extra) all.push_back(extra);
+    for (auto* y : all) {
+        double a, b;
+        species_freqs(*y, a, b);
+        wp2 += a;
+        wb2 = std::max(wb2, b);
+    }
+    const double m = std::max(1.0, einv_max);
+    double cs = 0.0;
+    for (int a = 0; a < s->g.dims; ++a) cs += 1.0 / (s->g.dx[a] * s->g.dx[a]);
+    const double lim = 1.0 / std::sqrt(0.25 * wb2 + 0.25 * m * wp2 + m * kC * kC * cs);
+    if (!(s->g.dt < lim)) return fail(s, PIC_ECFL, "dt %.6e is not below the stability limit %.6e", s->g.dt, lim);
+    return PIC_OK;
+}
+
 extern "C" int pic_init_species(pic_sim* s, const pic_species_desc* d, uint64_t seed, int* species_id)
 {
     if (!s || !d) return PIC_EINVAL;
@@ -375,23 +400,7 @@ extern "C" int pic_init_species(pic_sim* s, const pic_species_desc* d, uint64_t 
             for (auto& v : x.cdf) v /= tot;
         }
     }
-    // eq:dtlimit with all declared species (plasma frequencies add, largest resonance)
-    {
-        double wp2 = 0.0, wb2 = 0.0;
-        std::vector<SpeciesHost*> all;
-        for (auto& y : s->sp) all.push_back(&y);
-        all.push_back(&x);
-        for (auto* y : all) {
-            double a, b;
-            species_freqs(*y, a, b);
-            wp2 += a;
-            wb2 = std::max(wb2, b);
-        }
-        double cs = 0.0;
-        for (int a = 0; a < dims; ++a) cs += 1.0 / (s->g.dx[a] * s->g.dx[a]);
-        const double lim = 1.0 / std::sqrt(0.25 * wb2 + 0.25 * wp2 + kC * kC * cs);
-        if (!(s->g.dt < lim)) return fail(s, PIC_ECFL, "dt %.6e is not below the stability limit %.6e", s->g.dt, lim);
-    }
+    if (int r = check_dt(s, &x, s->einv_max)) return r;
     const int sid = (int)s->sp.size();
     s->sp.push_back(std::move(x));
     if (species_id) *species_id = sid;
@@ -502,6 +511,7 @@ static size_t plan(pic_sim* s, char* base, bool assign)
     h.rho_a = P.take<double>(L);
     h.rho_b = P.take<double>(L);
     h.jtrack = h.track ? P.takeb(3 * L * es) : nullptr;
+    h.einv = s->g.eps_cells ? P.takeb(3 * L * es) : nullptr;
     h.red = P.take<double>(16);
     s->part = P.take<double>(kDiagBlocks * 4);
     s->outv = P.take<double>(16);
@@ -635,6 +645,13 @@ extern "C" int pic_bind(pic_sim* s, void* dev_arena, size_t bytes, void* hip_str
     // persistent particle grid: a multiple of 8 (the XCD count) up to 8 workgroups per CU
     s->pgrid = std::max(8, (std::min(s->h.max_units, ncu * 8) + 7) / 8 * 8);
     HIPCHK(s, enqueue_fill(s->arena, need - kAlign, s->st));
+    if (s->h.einv) {
+        // the unit tensor until pic_load_eps_inv: 1.0f, or 1.0 as the words (0, 0x3ff00000)
+        const size_t nb = 3 * (size_t)s->h.Lvol * s->es;
+        if (s->es == 4) HIPCHK(s, enqueue_fill_pattern(s->h.einv, nb, 0x3f800000u, 0x3f800000u, s->st));
+        else HIPCHK(s, enqueue_fill_pattern(s->h.einv, nb, 0u, 0x3ff00000u, s->st));
+    }
+    s->einv_max = 1.0;
     int r = upload_table(s);
     if (r) return r;
     for (size_t i = 0; i < s->sp.size(); ++i) {
@@ -751,6 +768,30 @@ extern "C" int pic_load_fields(pic_sim* s, const double* e, const double* b)
     return PIC_OK;
 }
 
+extern "C" int pic_load_eps_inv(pic_sim* s, const double* einv)
+{
+    if (!s) return PIC_EINVAL;
+    if (!s->bound) return fail(s, PIC_ESTATE, "bind before loading the permittivity");
+    if (s->batch_refs) return fail(s, PIC_ESTATE, "simulation is in a batch");
+    if (!s->h.einv) return fail(s, PIC_EINVAL, "the grid was created with eps_cells = 0");
+    if (!einv) return fail(s, PIC_EINVAL, "null einv");
+    const size_t L = (size_t)s->h.Lvol;
+    double mx = 0.0;
+    for (size_t q = 0; q < 3 * L; ++q) {
+        if (!(einv[q] > 0.0) || !std::isfinite(einv[q])) return fail(s, PIC_EINVAL, "einv entry %zu is not finite and positive", q);
+        // the stored value must stay positive and finite in the working precision too
+        if (s->es == 4 && !(einv[q] >= 1e-30 && einv[q] <= 1e30)) return fail(s, PIC_EINVAL, "einv entry %zu out of FP32 range", q);
+        mx = std::max(mx, einv[q]);
+    }
+    if (int r = check_dt(s, nullptr, mx)) return r;
+    std::vector<char> buf;
+    if (s->es == 4) to_real<float>(einv, 3 * L, buf); else to_real<double>(einv, 3 * L, buf);
+    HIPCHK(s, hipMemcpyAsync(s->h.einv, buf.data(), buf.size(), hipMemcpyHostToDevice, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    s->einv_max = mx;
+    return PIC_OK;
+}
+
 static hipError_t launch_rho(pic_sim* s, double* rho)
 {
     hipError_t e = enqueue_fill(rho, sizeof(double) * (size_t)s->h.Lvol, s->st);
@@ -814,6 +855,7 @@ static Launch make_launch(pic_sim* s)
     L.pgrid = s->pgrid;
     L.block = s->g.block;
     L.ftiles_total = s->h.nftiles;
+    L.eps = s->h.einv != nullptr;
     L.stream = s->st;
     return L;
 }
@@ -1255,6 +1297,7 @@ static int batch_enqueue_period(pic_batch* b, std::vector<std::vector<int>>* sor
 {
     const int n = (int)b->members.size();
     int max_vf = 1, max_vj = 1, lds = 1, pgrid = 1, ft = 0, block = 64;
+    bool eps = false;
     for (int i = 0; i < n; ++i) {
         pic_sim* s = b->members[i];
         std::vector<int> mine;
@@ -1271,6 +1314,7 @@ static int batch_enqueue_period(pic_batch* b, std::vector<std::vector<int>>* sor
         pgrid = std::max(pgrid, s->pgrid);
         ft += s->h.nftiles;
         block = std::max(block, s->g.block);
+        eps = eps || s->h.einv != nullptr;
     }
     Launch L{};
     L.sims = b->table;
@@ -1280,6 +1324,7 @@ static int batch_enqueue_period(pic_batch* b, std::vector<std::vector<int>>* sor
     L.pgrid = pgrid;
     L.block = block;
     L.ftiles_total = ft;
+    L.eps = eps;
     L.stream = b->st;
     const int P = b->members[0]->g.sort_every;
     for (int k = 0; k < P; ++k) {

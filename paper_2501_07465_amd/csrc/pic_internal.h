@@ -119,6 +119,7 @@ struct SimDev {
     // diagnostics
     int track;             // keep the merged particle current of the last step
     void* jtrack;          // [3][Lvol] R
+    void* einv;            // [3][Lvol] R: inverse permittivity at the E_c nodes, or null (unit tensor)
     double* rho_ion;       // [Lvol]
     double* rho_a;         // [Lvol]
     double* rho_b;         // [Lvol]
@@ -159,6 +160,7 @@ struct Launch {
     int pgrid;             // particle-kernel grid
     int block;             // particle-kernel block
     int ftiles_total;      // field tiles over members
+    bool eps;              // some member has a per-cell inverse permittivity
     hipStream_t stream;
 };
 
@@ -187,6 +189,7 @@ struct Launchers {
 
 // Untyped helpers (pic_sort.hip).
 hipError_t enqueue_fill(void* p, size_t bytes, hipStream_t st);  // zero fill by kernel (graph safe)
+hipError_t enqueue_fill_pattern(void* p, size_t bytes, unsigned lo, unsigned hi, hipStream_t st);  // 64-bit pattern
 hipError_t enqueue_sum(const double* x, long long n, double* part, int nb, hipStream_t st);
 hipError_t enqueue_final(const double* part, int nb, int nv, int op, double* out, hipStream_t st);
 hipError_t enqueue_ion(SimDev* dS, const double* rho, int uniform, const double* total, hipStream_t st);

@@ -368,21 +368,24 @@ hipError_t enqueue_compact(SimDev* dS, hipStream_t st)
 namespace pic {
 
 // ---- untyped helpers ---------------------------------------------------------------------------
-__global__ void k_fill(unsigned* __restrict__ p, long long nwords)
+// even words get lo, odd words hi (a 64-bit pattern; lo == hi for a 32-bit one)
+__global__ void k_fill(unsigned* __restrict__ p, long long nwords, unsigned lo, unsigned hi)
 {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nwords; i += (long long)gridDim.x * blockDim.x)
-        p[i] = 0u;
+        p[i] = (i & 1) ? hi : lo;
 }
 
-hipError_t enqueue_fill(void* p, size_t bytes, hipStream_t st)
+hipError_t enqueue_fill_pattern(void* p, size_t bytes, unsigned lo, unsigned hi, hipStream_t st)
 {
     const long long nw = (long long)(bytes / 4);
     if (nw <= 0) return hipSuccess;
     long long g = (nw + 255) / 256;
     if (g > 16384) g = 16384;
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)g), dim3(256), 0, st, reinterpret_cast<unsigned*>(p), nw);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)g), dim3(256), 0, st, reinterpret_cast<unsigned*>(p), nw, lo, hi);
     return hipGetLastError();
 }
+
+hipError_t enqueue_fill(void* p, size_t bytes, hipStream_t st) { return enqueue_fill_pattern(p, bytes, 0u, 0u, st); }
 
 __global__ void __launch_bounds__(256) k_sum(const double* __restrict__ x, long long n, double* part)
 {

@@ -152,3 +152,47 @@ def test_periodic_axis_shorter_than_its_window_rejected():
     with pytest.raises(pic.PicError) as e:
         pic.pic_create(_grid(2, [3, 64, 1], [4, 8, 1]))
     assert e.value.code == pic.PIC_EINVAL
+
+
+def test_dielectric_arena_and_validation():
+    """eps_cells = 1 adds exactly the three inverse-permittivity arrays to the footprint; other values
+    are rejected; loading needs a bound simulation."""
+    from paper_2501_07465_amd import pic, workloads as W
+    for prec, es in (("fp32", 4), ("fp64", 8)):
+        w = W.small("disk2d")
+        h0 = pic.pic_create(pic.grid_desc(w, prec))
+        we = W.with_dielectric(w, [3.7, 3.7, 3.7])
+        g = pic.grid_desc(we, prec)
+        assert g.eps_cells == 1
+        h1 = pic.pic_create(g)
+        L = pic.pic_field_shape(h1)
+        extra = pic.pic_footprint(h1) - pic.pic_footprint(h0)
+        need = 3 * L[0] * L[1] * L[2] * es
+        assert need <= extra < need + 256
+        with pytest.raises(pic.PicError) as e:
+            pic.pic_load_eps_inv(h1, W.eps_inv_map(we))
+        assert e.value.code == pic.PIC_ESTATE
+        pic.pic_destroy(h0)
+        pic.pic_destroy(h1)
+    g = pic.grid_desc(W.small("disk2d"))
+    g.eps_cells = 2
+    with pytest.raises(pic.PicError) as e:
+        pic.pic_create(g)
+    assert e.value.code == pic.PIC_EINVAL
+
+
+def test_eps_inv_map_places_the_yee_nodes():
+    """The input map: component c is sampled half a cell along c (its Yee node)."""
+    from paper_2501_07465_amd import workloads as W
+    w = {"name": "m", "dims": 2, "n": [8, 6, 1], "dx": [1e-9] * 3, "dt": 1e-18, "periodic": [0, 1, 1],
+         "tile": [4, 2, 1], "species": [{"region": {"kind": "box", "lo": [2.0, 1.0, 0.0], "hi": [4.0, 3.0, 1.0]}}]}
+    m = W.eps_inv_map(W.with_dielectric(w, [2.0, 4.0, 8.0]))
+    assert m.shape == (3, 1, 6, 9)
+    # E_x at (i + 1/2, j): inside for i in {2, 3} (x in [2, 4)) and j in {1, 2}
+    assert set(zip(*np.nonzero(m[0, 0] != 1.0))) == {(j, i) for j in (1, 2) for i in (2, 3)}
+    assert np.all(m[0, 0][m[0, 0] != 1.0] == 0.5)
+    # E_y at (i, j + 1/2): j + 1/2 in [1, 3) -> j in {1, 2}; i in {2, 3}
+    assert set(zip(*np.nonzero(m[1, 0] != 1.0))) == {(j, i) for j in (1, 2) for i in (2, 3)}
+    # E_z at (i, j): i in {2, 3}, j in {1, 2}
+    assert np.all(m[2, 0][m[2, 0] != 1.0] == 0.125)
+    assert W.eps_inv_map(w) is None
