@@ -49,7 +49,7 @@ class Species(C.Structure):
                 ("omega0_sq", C.c_double * 3), ("gamma", C.c_double * 3), ("b_weight", C.c_double),
                 ("v_f", C.c_double), ("sheet_normal", C.c_int), ("reflect", C.c_int),
                 ("region", C.c_int), ("rc", C.c_double * 3), ("rr", C.c_double),
-                ("rlo", C.c_double * 3), ("rhi", C.c_double * 3)]
+                ("rlo", C.c_double * 3), ("rhi", C.c_double * 3), ("seed", C.c_uint64)]
 
 
 class Init(C.Structure):
@@ -82,6 +82,8 @@ def lib():
         L.or_boris_matrix.argtypes = [_D, _D]
         L.or_gyro_matrix.argtypes = [_D, _D, _D]
         L.or_reflect.argtypes = [C.POINTER(Species), C.c_int, _D, _D]
+        L.or_lambert.argtypes = [_D, _D, _D]
+        L.or_scatter_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _D]
         L.or_fd_sample_speeds.argtypes = [C.c_double, C.c_double, C.c_double, C.c_size_t, _D, _D]
         L.or_create.argtypes = [C.POINTER(Grid), C.POINTER(C.c_void_p)]
         L.or_destroy.argtypes = [C.c_void_p]
@@ -150,6 +152,18 @@ def push_dirac(qm, dt, v_f, normal, E, B, v):
     v = _v3(v).copy()
     lib().or_push_dirac(qm, dt, v_f, normal, _dp(_v3(E)), _dp(_v3(B)), _dp(v))
     return v
+
+
+def lambert(n, u, v):
+    n = _v3(n); u = np.ascontiguousarray(u, dtype=np.float64); v = _v3(v).copy()
+    lib().or_lambert(_dp(n), _dp(u), _dp(v))
+    return v
+
+
+def scatter_uniforms(seed, p, step, sid):
+    u = np.zeros(2)
+    lib().or_scatter_uniforms(seed, p, step, sid, _dp(u))
+    return u
 
 
 def boris_matrix(b):
@@ -222,7 +236,7 @@ def make_species(sp: dict, dims: int) -> Species:
     s.b_weight = sp.get("b_weight", 0.0)
     s.v_f = sp.get("v_f", 0.0)
     s.sheet_normal = sp.get("sheet_normal", -1)
-    s.reflect = int(sp.get("reflect", 0))
+    s.reflect = (2 if sp.get("scatter", "specular") == "diffuse" else 1) if sp.get("reflect", False) else 0
     reg = sp.get("region", {"kind": "all"})
     s.region = _REGION[reg["kind"]]
     for a in range(3):
@@ -277,6 +291,7 @@ class Sim:
     # -- particles ------------------------------------------------------------------------------
     def init_species(self, sp: dict, seed: int) -> int:
         s = make_species(sp, self.dims)
+        s.seed = seed
         ini = Init()
         ini.ppc = sp["ppc"]
         ini.momentum = 1 if sp.get("momentum", "fd") == "fd" else 0
@@ -295,8 +310,9 @@ class Sim:
         self.species.append(sp)
         return sid.value
 
-    def add_species(self, sp: dict, weight: float, x, v, xi=None) -> int:
+    def add_species(self, sp: dict, weight: float, x, v, xi=None, seed: int | None = None) -> int:
         s = make_species(sp, self.dims)
+        s.seed = self.w.get("seed", 1) if seed is None else seed
         s.weight = weight
         x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
         v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1, 3)

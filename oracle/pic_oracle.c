@@ -388,6 +388,60 @@ int or_reflect(const or_species* s, int dims, double X[3], double v[3])
 }
 
 /* ------------------------------------------------------------------------- */
+/* Diffusive scattering at the material boundary (Sec. 3 names specular and  */
+/* diffusive models; the paper gives no formula).  Reading: the collision is  */
+/* elastic, the position is mirrored as in the specular case, and the new    */
+/* direction follows the cosine law about the inward normal: cos(theta) =     */
+/* sqrt(u0), phi = 2 pi u1, on the basis (n, t1, t2) with t1 = n x e_k / |.|, */
+/* e_k the axis of the smallest |n_k| (lowest k on ties), t2 = n x t1.        */
+/* ------------------------------------------------------------------------- */
+void or_lambert(const double n[3], const double u[2], double v[3])
+{
+    double speed = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    int k = 0;
+    for (int a = 1; a < 3; ++a)
+        if (fabs(n[a]) < fabs(n[k])) k = a;
+    double e[3] = {0.0, 0.0, 0.0};
+    e[k] = 1.0;
+    double t1[3] = {n[1] * e[2] - n[2] * e[1], n[2] * e[0] - n[0] * e[2], n[0] * e[1] - n[1] * e[0]};
+    double l = sqrt(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]);
+    for (int a = 0; a < 3; ++a) t1[a] /= l;
+    double t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
+    double ct = sqrt(u[0]), st = sqrt(1.0 - u[0]);
+    double ph = 2.0 * PI * u[1];
+    double cp = cos(ph), sp = sin(ph);
+    for (int a = 0; a < 3; ++a) v[a] = speed * (ct * n[a] + st * (cp * t1[a] + sp * t2[a]));
+}
+
+void or_scatter_uniforms(uint64_t seed, uint32_t p, uint32_t step, uint32_t sid, double u[2])
+{
+    uint32_t ctr[4] = {p, step, sid, 0x80000000u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t r[4];
+    or_philox4x32_10(ctr, key, r);
+    u[0] = or_u53(r[0], r[1]);
+    u[1] = or_u53(r[2], r[3]);
+}
+
+/* Inward unit normal where a particle at X (cell units, outside its region)
+ * left it: ball, -(X - c)/|X - c|; box, the normalised sum of the inward
+ * normals of the faces it is beyond. */
+static void inward_normal(const or_species* s, int dims, const double X[3], double n[3])
+{
+    n[0] = n[1] = n[2] = 0.0;
+    if (s->region == OR_REGION_BALL) {
+        for (int a = 0; a < dims; ++a) n[a] = s->rc[a] - X[a];
+    } else {
+        for (int a = 0; a < dims; ++a) {
+            if (X[a] > s->rhi[a]) n[a] = -1.0;
+            else if (X[a] < s->rlo[a]) n[a] = 1.0;
+        }
+    }
+    double l = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    for (int a = 0; a < 3; ++a) n[a] /= l;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Simulation state                                                          */
 /* ------------------------------------------------------------------------- */
 #define OR_MAX_SPECIES 8
@@ -513,6 +567,9 @@ void or_destroy(or_sim* s)
 static int check_species(const or_sim* s, const or_species* sp)
 {
     if (sp->kind < OR_FREE || sp->kind > OR_DIRAC || sp->m <= 0.0) return -1;
+    if (sp->reflect < 0 || sp->reflect > 2) return -1;
+    /* diffusive draws are three-dimensional: free carriers only */
+    if (sp->reflect == 2 && sp->kind != OR_FREE) return -1;
     if (sp->region == OR_REGION_BALL)
         for (int a = 1; a < s->g.dims; ++a)
             if (s->g.dx[a] != s->g.dx[0]) return -1;
@@ -1173,8 +1230,16 @@ static void particle_step(or_sim* s, double I[3])
             } else if (sp->reflect) {
                 double X[3] = {0.0, 0.0, 0.0};
                 for (int a = 0; a < d; ++a) X[a] = (double)c0[a] + x1[a];
-                if (or_reflect(sp, d, X, v))
+                double n[3];
+                if (sp->reflect == 2) inward_normal(sp, d, X, n);  /* at the escaped point */
+                if (or_reflect(sp, d, X, v)) {
                     for (int a = 0; a < d; ++a) x1[a] = X[a] - (double)c0[a];
+                    if (sp->reflect == 2) {
+                        double u[2];
+                        or_scatter_uniforms(sp->seed, (uint32_t)p, (uint32_t)s->step, (uint32_t)isp, u);
+                        or_lambert(n, u, v);
+                    }
+                }
             }
             deposit(s, qw, c0, x0, x1, v);
             for (int a = 0; a < 3; ++a) I[a] += qw * v[a];

@@ -59,10 +59,12 @@ typedef struct {
     double b_weight;     /* bound: 0 (magnetic force off) or 1 (gyrotropic)   */
     double v_f;          /* Dirac: Fermi speed [m/s]                          */
     int sheet_normal;    /* Dirac: axis whose velocity component is removed, or -1 */
-    int reflect;         /* 1: specular reflection at the region boundary     */
+    int reflect;         /* 0: none; 1: specular, 2: diffusive (Lambert) scattering */
+                         /* at the region boundary (Sec. 3)                   */
     int region;          /* OR_REGION_*                                       */
     double rc[3], rr;    /* ball centre and radius [cells]                    */
     double rlo[3], rhi[3]; /* box corners [cells]                             */
+    uint64_t seed;       /* Philox key of the diffusive draws                 */
 } or_species;
 
 typedef struct {
@@ -102,6 +104,13 @@ void or_push_bound(double qm, double dt, const double w2[3], const double gam[3]
 void or_push_dirac(double qm, double dt, double v_f, int normal,
                    const double E[3], const double B[3], double v[3]);
 int  or_reflect(const or_species* s, int dims, double X[3], double v[3]);
+/* Diffusive scattering of a reflected particle: the speed |v| kept, the direction
+ * drawn from the cosine (Lambert) law about the inward unit normal n, with the
+ * two uniforms u[0], u[1] in (0,1). */
+void or_lambert(const double n[3], const double u[2], double v[3]);
+/* The two uniforms of the diffusive draw of particle p of species sid in step
+ * `step` (Philox4x32-10, counter (p, step, sid, 0x80000000), key seed). */
+void or_scatter_uniforms(uint64_t seed, uint32_t p, uint32_t step, uint32_t sid, double u[2]);
 int  or_fd_sample_speeds(double e_fermi, double kT, double mass, size_t n,
                          const double* u, double* speed);
 

@@ -198,6 +198,17 @@ def with_dielectric(w: dict, eps, region=None) -> dict:
     return w
 
 
+def with_diffuse_walls(w: dict) -> dict:
+    """A copy of workload w whose reflecting species scatter diffusively (cosine law) instead of
+    specularly at their region boundary."""
+    w = copy.deepcopy(w)
+    for sp in w["species"]:
+        if sp.get("reflect"):
+            sp["scatter"] = "diffuse"
+    w["name"] = w["name"] + "_diffuse"
+    return w
+
+
 def field_extent(w: dict):
     """Array extent per axis of a field component: n on periodic and inactive axes, n + 1 on open ones."""
     return [w["n"][a] + (1 if a < w["dims"] and not w["periodic"][a] else 0) for a in range(3)]
