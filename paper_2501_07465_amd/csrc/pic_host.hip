@@ -328,6 +328,8 @@ extern "C" int pic_init_species(pic_sim* s, const pic_species_desc* d, uint64_t 
     if (d->kind < PIC_FREE || d->kind > PIC_DIRAC) return fail(s, PIC_EINVAL, "species kind");
     if (!(d->q != 0.0) || !std::isfinite(d->q)) return fail(s, PIC_EINVAL, "charge");
     if (d->region < PIC_REGION_ALL || d->region > PIC_REGION_BOX) return fail(s, PIC_EINVAL, "region");
+    if (d->reflect < 0 || d->reflect > 2) return fail(s, PIC_EINVAL, "reflect must be 0, 1 or 2");
+    if (d->reflect == 2 && d->kind != PIC_FREE) return fail(s, PIC_EINVAL, "diffusive walls are for free species");
     if (d->region == PIC_REGION_BALL)
         for (int a = 1; a < dims; ++a)
             if (s->g.dx[a] != s->g.dx[0]) return fail(s, PIC_EINVAL, "ball regions need equal cell sizes");
@@ -552,7 +554,8 @@ static void mirror_species(pic_sim* s, int i)
     SpeciesDev& d = s->h.sp[i];
     const auto& D = x.d;
     d.kind = D.kind;
-    d.reflect = D.reflect ? 1 : 0;
+    d.reflect = D.reflect;
+    d.seed = x.seed;
     d.region = D.region;
     d.sheet_normal = D.kind == PIC_DIRAC ? D.sheet_normal : -1;
     d.n = (int)x.n;
@@ -845,6 +848,13 @@ static int enqueue_sort_all(pic_sim* s, std::vector<int>* sorted)
     return PIC_OK;
 }
 
+static bool has_diffuse(const pic_sim* s)
+{
+    for (const auto& x : s->sp)
+        if (x.d.reflect == 2) return true;
+    return false;
+}
+
 static Launch make_launch(pic_sim* s)
 {
     Launch L{};
@@ -856,6 +866,7 @@ static Launch make_launch(pic_sim* s)
     L.block = s->g.block;
     L.ftiles_total = s->h.nftiles;
     L.eps = s->h.einv != nullptr;
+    L.diffuse = has_diffuse(s);
     L.stream = s->st;
     return L;
 }
@@ -1297,7 +1308,7 @@ static int batch_enqueue_period(pic_batch* b, std::vector<std::vector<int>>* sor
 {
     const int n = (int)b->members.size();
     int max_vf = 1, max_vj = 1, lds = 1, pgrid = 1, ft = 0, block = 64;
-    bool eps = false;
+    bool eps = false, diffuse = false;
     for (int i = 0; i < n; ++i) {
         pic_sim* s = b->members[i];
         std::vector<int> mine;
@@ -1315,6 +1326,7 @@ static int batch_enqueue_period(pic_batch* b, std::vector<std::vector<int>>* sor
         ft += s->h.nftiles;
         block = std::max(block, s->g.block);
         eps = eps || s->h.einv != nullptr;
+        diffuse = diffuse || has_diffuse(s);
     }
     Launch L{};
     L.sims = b->table;
@@ -1325,6 +1337,7 @@ static int batch_enqueue_period(pic_batch* b, std::vector<std::vector<int>>* sor
     L.block = block;
     L.ftiles_total = ft;
     L.eps = eps;
+    L.diffuse = diffuse;
     L.stream = b->st;
     const int P = b->members[0]->g.sort_every;
     for (int k = 0; k < P; ++k) {

@@ -59,6 +59,7 @@ struct SpeciesDev {
     double bw;             // bound: weight of the magnetic force
     double vf;             // Dirac: Fermi speed
     double rc[3], rr, rlo[3], rhi[3];  // region (cell units)
+    unsigned long long seed;           // Philox key of the loader and of diffusive wall draws
     // state, structure of arrays; R = float or double by precision
     int* cell;             // packed cell index (free/Dirac: current cell; bound: anchor cell)
     void* off[3];          // in-cell offset in [0,1) (bound: anchor offset)
@@ -161,6 +162,7 @@ struct Launch {
     int block;             // particle-kernel block
     int ftiles_total;      // field tiles over members
     bool eps;              // some member has a per-cell inverse permittivity
+    bool diffuse;          // some member has a species with diffusive walls
     hipStream_t stream;
 };
 

@@ -311,7 +311,7 @@ def species_desc(sp: dict, count: int = 0, weight: float = 0.0) -> SpeciesDesc:
     d.xi_radius = sp.get("xi_radius", 0.0)
     d.v_f = sp.get("v_f", 0.0)
     d.sheet_normal = sp.get("sheet_normal", -1)
-    d.reflect = int(bool(sp.get("reflect", False)))
+    d.reflect = (2 if sp.get("scatter", "specular") == "diffuse" else 1) if sp.get("reflect", False) else 0
     reg = sp.get("region", {"kind": "all"})
     d.region = _REGION[reg["kind"]]
     for a in range(3):
