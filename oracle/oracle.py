@@ -101,6 +101,7 @@ def lib():
         L.or_get_fields.argtypes = [C.c_void_p, _D, _D]
         L.or_set_fields.argtypes = [C.c_void_p, _D, _D]
         L.or_set_eps_inv.argtypes = [C.c_void_p, _D]
+        L.or_set_ext_field.argtypes = [C.c_void_p, _D]
         L.or_get_current.argtypes = [C.c_void_p, _D]
         L.or_get_rho.argtypes = [C.c_void_p, _D]
         L.or_gather_at.argtypes = [C.c_void_p, _D, _D, _D]
@@ -371,6 +372,17 @@ class Sim:
         b = np.ascontiguousarray(b, dtype=np.float64).ravel()
         lib().or_set_fields(self.h, _dp(e), _dp(b))
 
+    def set_ext_field(self, e):
+        """Static external field e[3][L] at the E_c nodes (Sec. 3 work-function barrier); None
+        removes it."""
+        if e is None:
+            rc = lib().or_set_ext_field(self.h, None)
+        else:
+            e = np.ascontiguousarray(e, dtype=np.float64).ravel()
+            rc = lib().or_set_ext_field(self.h, _dp(e))
+        if rc != 0:
+            raise ValueError("or_set_ext_field failed (%d)" % rc)
+
     def set_eps_inv(self, einv):
         """Diagonal inverse permittivity einv[3][L] at the E_c nodes (Sec. 4,
         eq:consteps); None restores the unit tensor."""
@@ -455,10 +467,14 @@ def build_workload(w: dict, seed: int | None = None) -> Sim:
     seed = w.get("seed", 1) if seed is None else seed
     for sp in w["species"]:
         s.init_species(sp, seed)
-    if w.get("dielectric") is not None:
-        # the inverse-permittivity map is an input, drawn by the shared input generator
+    if w.get("dielectric") is not None or w.get("wall") is not None:
+        # the inverse-permittivity map and the wall field are inputs, drawn by the shared input
+        # generator
         from paper_2501_07465_amd import workloads as W
-        s.set_eps_inv(W.eps_inv_map(w))
+        if w.get("dielectric") is not None:
+            s.set_eps_inv(W.eps_inv_map(w))
+        if w.get("wall") is not None:
+            s.set_ext_field(W.wall_field(w))
     s.set_ion_background(w.get("ion", "local") == "uniform")
     if w.get("gauss_init", False):
         s.gauss_init_1d()

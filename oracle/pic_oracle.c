@@ -467,6 +467,7 @@ struct or_sim {
     double* B[3];
     double* J[3];    /* particle current of the last step, J^{n+1/2}         */
     double* einv[3]; /* inverse permittivity at the E_c nodes (NULL: unit)   */
+    double* eext[3]; /* static external field at the E_c nodes (NULL: none)  */
     double* rho_ion; /* fixed background charge density at nodes            */
     int have_ion;
     int nsp;
@@ -557,7 +558,9 @@ int or_create(const or_grid* g, or_sim** out)
 void or_destroy(or_sim* s)
 {
     if (!s) return;
-    for (int c = 0; c < 3; ++c) { free(s->E[c]); free(s->B[c]); free(s->J[c]); free(s->einv[c]); }
+    for (int c = 0; c < 3; ++c) {
+        free(s->E[c]); free(s->B[c]); free(s->J[c]); free(s->einv[c]); free(s->eext[c]);
+    }
     free(s->rho_ion);
     for (int i = 0; i < s->nsp; ++i) { free(s->sp[i].C); free(s->sp[i].O); free(s->sp[i].v); free(s->sp[i].xi); }
     free(s->series);
@@ -895,11 +898,14 @@ static double gather(const or_sim* s, const double* F, const int half[3], const 
     return sum;
 }
 
+/* The particles feel E + E_ext: the static external (work-function) field of Sec. 3 sits on the
+ * E nodes, is gathered like E and never enters the Maxwell update. */
 static void gather_EB(const or_sim* s, const long C[3], const double O[3], double E[3], double B[3])
 {
     int h[3];
     for (int c = 0; c < 3; ++c) {
         stag_E(c, h); E[c] = gather(s, s->E[c], h, C, O);
+        if (s->eext[c]) E[c] += gather(s, s->eext[c], h, C, O);
         stag_B(c, h); B[c] = gather(s, s->B[c], h, C, O);
     }
 }
@@ -1325,6 +1331,22 @@ int or_set_fields(or_sim* s, const double* e, const double* b)
     for (int c = 0; c < 3; ++c) {
         if (e) memcpy(s->E[c], e + c * s->len, sizeof(double) * s->len);
         if (b) memcpy(s->B[c], b + c * s->len, sizeof(double) * s->len);
+    }
+    return 0;
+}
+
+int or_set_ext_field(or_sim* s, const double* e)
+{
+    if (e)
+        for (size_t q = 0; q < 3 * s->len; ++q)
+            if (!isfinite(e[q])) return -1;
+    for (int c = 0; c < 3; ++c) {
+        free(s->eext[c]);
+        s->eext[c] = NULL;
+        if (!e) continue;
+        s->eext[c] = (double*)malloc(sizeof(double) * s->len);
+        if (!s->eext[c]) return -2;
+        memcpy(s->eext[c], e + c * s->len, sizeof(double) * s->len);
     }
     return 0;
 }

@@ -131,6 +131,10 @@ int  or_get_fields(const or_sim* s, double* e, double* b);   /* [3][L] each */
  * einv[3][L] holds the inverse permittivity of component c at the E_c node
  * (NULL restores the unit tensor).  Entries must be finite and positive. */
 int  or_set_eps_inv(or_sim* s, const double* einv);
+/* Sec. 3: a static external electrostatic field e[3][L] at the E_c nodes (the
+ * work-function barrier), felt by the particles (gathered like E) and outside
+ * the Maxwell update and the field diagnostics.  NULL removes it. */
+int  or_set_ext_field(or_sim* s, const double* e);
 int  or_set_fields(or_sim* s, const double* e, const double* b);
 int  or_get_current(const or_sim* s, double* j);             /* last particle J, [3][L] */
 int  or_get_rho(const or_sim* s, double* rho);               /* particle rho at nodes, [L] */

@@ -209,6 +209,62 @@ def with_diffuse_walls(w: dict) -> dict:
     return w
 
 
+def with_potential_wall(w: dict, height_ev: float, width: float, region=None) -> dict:
+    """A copy of workload w whose free species are held by a static work-function barrier instead
+    of reflecting walls: the potential energy of an electron rises by height_ev linearly over
+    `width` cells outside region (default: the first species' region).  The grid becomes periodic
+    on every axis (free particles without walls may reach any cell)."""
+    w = copy.deepcopy(w)
+    w["wall"] = {"height_ev": float(height_ev), "width": float(width),
+                 "region": copy.deepcopy(region or w["species"][0]["region"])}
+    for sp in w["species"]:
+        if sp["kind"] == "free":
+            sp["reflect"] = False
+    w["periodic"] = [1, 1, 1]
+    w["name"] = w["name"] + "_wall"
+    return w
+
+
+def wall_field(w: dict):
+    """The barrier field at the E nodes ([3][L2][L1][L0], V/m): E = -grad phi on the grid, with the
+    node potential phi = -height_ev * clamp(d / width, 0, 1) volts and d the distance (cells) of
+    the node outside the region (so an electron's energy -e phi rises by height_ev eV).  Component
+    c at node i holds -(phi(i + e_c) - phi(i)) / dx_c (wrapped on periodic axes, 0 on the padding
+    index of an open axis and on inactive axes).  None without a wall."""
+    d = w.get("wall")
+    if d is None:
+        return None
+    L = field_extent(w)
+    dims = w["dims"]
+    kk, jj, ii = np.meshgrid(np.arange(L[2], dtype=float), np.arange(L[1], dtype=float),
+                             np.arange(L[0], dtype=float), indexing="ij")
+    pos = [ii, jj, kk]
+    reg = d["region"]
+    if reg["kind"] == "ball":
+        dist = np.sqrt(sum((pos[a] - reg["center"][a]) ** 2 for a in range(dims))) - reg["radius"]
+    elif reg["kind"] == "box":
+        out = np.zeros_like(ii)
+        for a in range(dims):
+            g = np.maximum(np.maximum(reg["lo"][a] - pos[a], pos[a] - reg["hi"][a]), 0.0)
+            out = out + g * g
+        dist = np.sqrt(out)
+    else:
+        dist = np.full_like(ii, -1.0)
+    phi = -d["height_ev"] * np.clip(dist / d["width"], 0.0, 1.0)
+    e = np.zeros((3,) + phi.shape)
+    for c in range(dims):
+        ax = 2 - c  # arrays are [z, y, x]
+        if w["periodic"][c]:
+            e[c] = -(np.roll(phi, -1, axis=ax) - phi) / w["dx"][c]
+        else:
+            sl_lo = [slice(None)] * 3
+            sl_hi = [slice(None)] * 3
+            sl_lo[ax] = slice(0, L[c] - 1)
+            sl_hi[ax] = slice(1, L[c])
+            e[c][tuple(sl_lo)] = -(phi[tuple(sl_hi)] - phi[tuple(sl_lo)]) / w["dx"][c]
+    return e
+
+
 def field_extent(w: dict):
     """Array extent per axis of a field component: n on periodic and inactive axes, n + 1 on open ones."""
     return [w["n"][a] + (1 if a < w["dims"] and not w["periodic"][a] else 0) for a in range(3)]
