@@ -83,6 +83,8 @@ typedef struct {
     int eps_cells;      /* 1: a per-cell diagonal inverse permittivity (eq:consteps) scales  */
                         /* the E update; set by pic_load_eps_inv, unit until then.           */
                         /* 0: the unit tensor (no arena space, no extra reads)               */
+    int ext_field;      /* 1: a static external field (pic_load_ext_field; zero until then)   */
+                        /* is added to E where the particles gather it                        */
 } pic_grid_desc;
 
 /* A species.  Free carriers follow eq:tradlorentz, bound ones eq:modlorentz
@@ -168,6 +170,15 @@ int pic_load_fields(pic_sim* s, const double* e, const double* b);
  * Synchronous.  Errors: PIC_EINVAL (eps_cells = 0, null or bad entries),
  * PIC_ECFL, PIC_ESTATE (not bound, or in a batch), PIC_EDEVICE. */
 int pic_load_eps_inv(pic_sim* s, const double* einv);
+
+/* Sec. 3: set the static external electrostatic field (the work-function
+ * barrier) e[3][L] (FP64 V/m, L the extent of pic_field_shape), entry
+ * [c][k][j][i] at the E_c node.  The particles feel E + e (the sum is formed
+ * on the E nodes before the gather); the Maxwell update, the field energy and
+ * the Gauss residual do not see it.  Needs ext_field = 1; zero until this
+ * call.  Synchronous.  Errors: PIC_EINVAL (ext_field = 0, null or non-finite
+ * entries), PIC_ESTATE (not bound, or in a batch), PIC_EDEVICE. */
+int pic_load_ext_field(pic_sim* s, const double* e);
 
 /* Array extent per axis of every field component: n for periodic (and
  * inactive) axes, n + 1 for open axes.  Component c of E sits at a half-integer

@@ -148,6 +148,7 @@ static int setup_grid(pic_sim* s)
     if (g.series_cap <= 0) g.series_cap = 8192;
     if (g.unit < 0 || (g.unit > 0 && g.unit < 64)) return fail(s, PIC_EINVAL, "unit must be 0 or >= 64");
     if (g.eps_cells != 0 && g.eps_cells != 1) return fail(s, PIC_EINVAL, "eps_cells must be 0 or 1");
+    if (g.ext_field != 0 && g.ext_field != 1) return fail(s, PIC_EINVAL, "ext_field must be 0 or 1");
     memset(&h, 0, sizeof(h));
     h.unit_cap = g.unit;
     h.dims = g.dims;
@@ -514,6 +515,7 @@ static size_t plan(pic_sim* s, char* base, bool assign)
     h.rho_b = P.take<double>(L);
     h.jtrack = h.track ? P.takeb(3 * L * es) : nullptr;
     h.einv = s->g.eps_cells ? P.takeb(3 * L * es) : nullptr;
+    h.eext = s->g.ext_field ? P.takeb(3 * L * es) : nullptr;
     h.red = P.take<double>(16);
     s->part = P.take<double>(kDiagBlocks * 4);
     s->outv = P.take<double>(16);
@@ -795,6 +797,24 @@ extern "C" int pic_load_eps_inv(pic_sim* s, const double* einv)
     return PIC_OK;
 }
 
+extern "C" int pic_load_ext_field(pic_sim* s, const double* e)
+{
+    if (!s) return PIC_EINVAL;
+    if (!s->bound) return fail(s, PIC_ESTATE, "bind before loading the external field");
+    if (s->batch_refs) return fail(s, PIC_ESTATE, "simulation is in a batch");
+    if (!s->h.eext) return fail(s, PIC_EINVAL, "the grid was created with ext_field = 0");
+    if (!e) return fail(s, PIC_EINVAL, "null field");
+    const size_t L = (size_t)s->h.Lvol;
+    for (size_t q = 0; q < 3 * L; ++q)
+        if (!std::isfinite(e[q]) || (s->es == 4 && !(std::fabs(e[q]) < 3e38)))
+            return fail(s, PIC_EINVAL, "external field entry %zu is not finite", q);
+    std::vector<char> buf;
+    if (s->es == 4) to_real<float>(e, 3 * L, buf); else to_real<double>(e, 3 * L, buf);
+    HIPCHK(s, hipMemcpyAsync(s->h.eext, buf.data(), buf.size(), hipMemcpyHostToDevice, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return PIC_OK;
+}
+
 static hipError_t launch_rho(pic_sim* s, double* rho)
 {
     hipError_t e = enqueue_fill(rho, sizeof(double) * (size_t)s->h.Lvol, s->st);
@@ -867,6 +887,7 @@ static Launch make_launch(pic_sim* s)
     L.ftiles_total = s->h.nftiles;
     L.eps = s->h.einv != nullptr;
     L.diffuse = has_diffuse(s);
+    L.ext = s->h.eext != nullptr;
     L.stream = s->st;
     return L;
 }
@@ -1308,7 +1329,7 @@ static int batch_enqueue_period(pic_batch* b, std::vector<std::vector<int>>* sor
 {
     const int n = (int)b->members.size();
     int max_vf = 1, max_vj = 1, lds = 1, pgrid = 1, ft = 0, block = 64;
-    bool eps = false, diffuse = false;
+    bool eps = false, diffuse = false, ext = false;
     for (int i = 0; i < n; ++i) {
         pic_sim* s = b->members[i];
         std::vector<int> mine;
@@ -1327,6 +1348,7 @@ static int batch_enqueue_period(pic_batch* b, std::vector<std::vector<int>>* sor
         block = std::max(block, s->g.block);
         eps = eps || s->h.einv != nullptr;
         diffuse = diffuse || has_diffuse(s);
+        ext = ext || s->h.eext != nullptr;
     }
     Launch L{};
     L.sims = b->table;
@@ -1338,6 +1360,7 @@ static int batch_enqueue_period(pic_batch* b, std::vector<std::vector<int>>* sor
     L.ftiles_total = ft;
     L.eps = eps;
     L.diffuse = diffuse;
+    L.ext = ext;
     L.stream = b->st;
     const int P = b->members[0]->g.sort_every;
     for (int k = 0; k < P; ++k) {

@@ -121,6 +121,7 @@ struct SimDev {
     int track;             // keep the merged particle current of the last step
     void* jtrack;          // [3][Lvol] R
     void* einv;            // [3][Lvol] R: inverse permittivity at the E_c nodes, or null (unit tensor)
+    void* eext;            // [3][Lvol] R: static external field at the E_c nodes felt by the particles, or null
     double* rho_ion;       // [Lvol]
     double* rho_a;         // [Lvol]
     double* rho_b;         // [Lvol]
@@ -163,6 +164,7 @@ struct Launch {
     int ftiles_total;      // field tiles over members
     bool eps;              // some member has a per-cell inverse permittivity
     bool diffuse;          // some member has a species with diffusive walls
+    bool ext;              // some member has a static external field
     hipStream_t stream;
 };
 

@@ -33,7 +33,7 @@ PIC_SRC_NONE, PIC_SRC_SHEET, PIC_SRC_POINT = 0, 1, 2
  DIAG_EXPORT_CURRENT, DIAG_KEYS) = range(12)
 
 EXPORTED = ["pic_create", "pic_init_species", "pic_footprint", "pic_bind", "pic_load_particles",
-            "pic_load_fields", "pic_load_eps_inv", "pic_field_shape", "pic_init_fields", "pic_step", "pic_use_graphs",
+            "pic_load_fields", "pic_load_eps_inv", "pic_load_ext_field", "pic_field_shape", "pic_init_fields", "pic_step", "pic_use_graphs",
             "pic_diag", "pic_time_kernels", "pic_sync", "pic_species_count", "pic_last_error", "pic_destroy",
             "pic_batch_footprint", "pic_batch_create", "pic_batch_add", "pic_batch_remove",
             "pic_batch_step", "pic_batch_size", "pic_batch_last_error", "pic_batch_destroy"]
@@ -46,7 +46,7 @@ class GridDesc(C.Structure):
                 ("sort_every", C.c_int), ("series_cap", C.c_int), ("track_continuity", C.c_int),
                 ("src_kind", C.c_int), ("src_comp", C.c_int), ("src_axis", C.c_int),
                 ("src_index", C.c_int * 3), ("src_j0", C.c_double), ("src_omega", C.c_double),
-                ("src_tau", C.c_double), ("eps_cells", C.c_int)]
+                ("src_tau", C.c_double), ("eps_cells", C.c_int), ("ext_field", C.c_int)]
 
 
 class SpeciesDesc(C.Structure):
@@ -84,6 +84,7 @@ def lib():
         L.pic_load_particles.argtypes = [_VP, C.c_int, _D, _D, _D, C.c_size_t]
         L.pic_load_fields.argtypes = [_VP, _D, _D]
         L.pic_load_eps_inv.argtypes = [_VP, _D]
+        L.pic_load_ext_field.argtypes = [_VP, _D]
         L.pic_field_shape.argtypes = [_VP, C.POINTER(C.c_int)]
         L.pic_init_fields.argtypes = [_VP, C.c_int]
         L.pic_step.argtypes = [_VP, C.c_int]
@@ -166,6 +167,11 @@ def pic_load_fields(h, e=None, b=None):
 def pic_load_eps_inv(h, einv):
     einv = np.ascontiguousarray(einv, dtype=np.float64)
     _check(lib().pic_load_eps_inv(h, einv.ctypes.data_as(_D)), h)
+
+
+def pic_load_ext_field(h, e):
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    _check(lib().pic_load_ext_field(h, e.ctypes.data_as(_D)), h)
 
 
 def pic_field_shape(h):
@@ -276,6 +282,7 @@ def grid_desc(w: dict, precision: str | None = None, track_continuity: bool = Fa
     g.series_cap = series_cap or max(1, int(w.get("steps", 1000)) + 64)
     g.track_continuity = int(track_continuity)
     g.eps_cells = int(w.get("dielectric") is not None)
+    g.ext_field = int(w.get("wall") is not None)
     src = w.get("source", {"kind": "none"})
     g.src_kind = _SRC[src["kind"]]
     if g.src_kind:
@@ -358,6 +365,9 @@ class Simulation:
         if w.get("dielectric") is not None:
             from . import workloads
             pic_load_eps_inv(self.h, workloads.eps_inv_map(w))
+        if w.get("wall") is not None:
+            from . import workloads
+            pic_load_ext_field(self.h, workloads.wall_field(w))
         if fields is not None:
             pic_load_fields(self.h, fields[0], fields[1])
         if init_fields:
