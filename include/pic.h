@@ -232,6 +232,15 @@ enum {
 };
 int pic_diag(pic_sim* s, int kind, int arg, double* out, size_t cap, size_t* n_out);
 
+/* Sec. 2 relaxation study: histogram of the macroparticle kinetic energies
+ * m |v|^2 / 2 (FP64 from the stored velocities) of species sid, counts[b] for
+ * b < nbins the energies in [b, b + 1) * e_max / nbins joules, counts[nbins]
+ * those at or above e_max (nbins + 1 entries, host memory).  Macroparticles
+ * are counted, not weighted.  Synchronises.  Errors: PIC_EINVAL (species id,
+ * nbins outside 1 .. 4096, e_max not positive, null counts), PIC_ESTATE,
+ * PIC_EDEVICE. */
+int pic_energy_histogram(pic_sim* s, int sid, double e_max, int nbins, uint64_t* counts);
+
 /* Run nsteps plain (non-graph) steps with HIP events recorded on the bound
  * stream around each launch and return average device times in milliseconds:
  * out[0] particle kernel, out[1] field kernel, out[2] one cell sort of all

@@ -102,6 +102,7 @@ def lib():
         L.or_set_fields.argtypes = [C.c_void_p, _D, _D]
         L.or_set_eps_inv.argtypes = [C.c_void_p, _D]
         L.or_set_ext_field.argtypes = [C.c_void_p, _D]
+        L.or_energy_histogram.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int, C.POINTER(C.c_uint64)]
         L.or_get_current.argtypes = [C.c_void_p, _D]
         L.or_get_rho.argtypes = [C.c_void_p, _D]
         L.or_gather_at.argtypes = [C.c_void_p, _D, _D, _D]
@@ -371,6 +372,14 @@ class Sim:
         e = np.ascontiguousarray(e, dtype=np.float64).ravel()
         b = np.ascontiguousarray(b, dtype=np.float64).ravel()
         lib().or_set_fields(self.h, _dp(e), _dp(b))
+
+    def energy_histogram(self, sid, e_max, nbins):
+        """Macroparticle kinetic-energy histogram: nbins bins over [0, e_max) J, then the overflow."""
+        out = np.zeros(nbins + 1, dtype=np.uint64)
+        r = lib().or_energy_histogram(self.h, sid, e_max, nbins, out.ctypes.data_as(C.POINTER(C.c_uint64)))
+        if r:
+            raise ValueError("or_energy_histogram failed")
+        return out
 
     def set_ext_field(self, e):
         """Static external field e[3][L] at the E_c nodes (Sec. 3 work-function barrier); None

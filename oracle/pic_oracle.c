@@ -1488,6 +1488,25 @@ double or_gauss_residual(const or_sim* s, double* scale)
     return res;
 }
 
+/* Sec. 2 relaxation study: histogram of the macroparticle kinetic energies
+ * 0.5 m |v|^2 of species sid in nbins equal bins over [0, e_max) (joules);
+ * counts[nbins] takes the energies at or above e_max.  Reading: the paper
+ * histograms macroparticles (not weighted by the real-particle weight). */
+int or_energy_histogram(const or_sim* s, int sid, double e_max, int nbins, uint64_t* counts)
+{
+    if (sid < 0 || sid >= s->nsp || nbins < 1 || !(e_max > 0.0)) return -1;
+    const sp_state* st = &s->sp[sid];
+    for (int b = 0; b <= nbins; ++b) counts[b] = 0;
+    for (size_t p = 0; p < st->n; ++p) {
+        const double* v = &st->v[3 * p];
+        double e = 0.5 * st->sp.m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        double f = e / e_max * (double)nbins;
+        long b = f >= (double)nbins ? nbins : (long)f;
+        counts[b] += 1;
+    }
+    return 0;
+}
+
 int or_current_series(const or_sim* s, double* out, size_t cap, size_t* n)
 {
     if (n) *n = s->series_n;

@@ -131,6 +131,9 @@ int  or_get_fields(const or_sim* s, double* e, double* b);   /* [3][L] each */
  * einv[3][L] holds the inverse permittivity of component c at the E_c node
  * (NULL restores the unit tensor).  Entries must be finite and positive. */
 int  or_set_eps_inv(or_sim* s, const double* einv);
+/* Sec. 2 relaxation study: macroparticle kinetic-energy histogram of species
+ * sid, nbins bins over [0, e_max) joules plus counts[nbins] at or above it. */
+int  or_energy_histogram(const or_sim* s, int sid, double e_max, int nbins, uint64_t* counts);
 /* Sec. 3: a static external electrostatic field e[3][L] at the E_c nodes (the
  * work-function barrier), felt by the particles (gathered like E) and outside
  * the Maxwell update and the field diagnostics.  NULL removes it. */

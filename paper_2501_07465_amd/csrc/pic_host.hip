@@ -517,6 +517,7 @@ static size_t plan(pic_sim* s, char* base, bool assign)
     h.einv = s->g.eps_cells ? P.takeb(3 * L * es) : nullptr;
     h.eext = s->g.ext_field ? P.takeb(3 * L * es) : nullptr;
     h.red = P.take<double>(16);
+    h.hist = P.take<unsigned long long>(kMaxHistBins + 1);
     s->part = P.take<double>(kDiagBlocks * 4);
     s->outv = P.take<double>(16);
     s->cont = P.take<double>(2);
@@ -565,6 +566,7 @@ static void mirror_species(pic_sim* s, int i)
     d.qm = D.q / x.mass;
     d.qw = D.q * x.weight;
     d.mw = x.mass * x.weight;
+    d.mass = x.mass;
     for (int a = 0; a < 3; ++a) {
         d.w2[a] = D.kind == PIC_BOUND ? D.omega0[a] * D.omega0[a] : 0.0;
         d.gam[a] = D.kind == PIC_BOUND ? D.gamma[a] : 0.0;
@@ -1084,6 +1086,25 @@ static int fetch_real(pic_sim* s, const void* src, size_t n, double* dst, size_t
 static int fetch_doubles(pic_sim* s, const double* src, size_t n, double* dst)
 {
     HIPCHK(s, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return PIC_OK;
+}
+
+extern "C" int pic_energy_histogram(pic_sim* s, int sid, double e_max, int nbins, uint64_t* counts)
+{
+    if (!s) return PIC_EINVAL;
+    if (!s->bound) return fail(s, PIC_ESTATE, "bind first");
+    if (sid < 0 || sid >= (int)s->sp.size()) return fail(s, PIC_EINVAL, "species id");
+    if (nbins < 1 || nbins > kMaxHistBins) return fail(s, PIC_EINVAL, "nbins must be 1 .. %d", kMaxHistBins);
+    if (!(e_max > 0.0) || !std::isfinite(e_max)) return fail(s, PIC_EINVAL, "e_max must be positive");
+    if (!counts) return fail(s, PIC_EINVAL, "null counts");
+    HIPCHK(s, enqueue_fill(s->h.hist, sizeof(unsigned long long) * (size_t)(nbins + 1), s->st));
+    if (s->sp[sid].n > 0) {
+        if (s->es == 4) HIPCHK(s, Launchers<float>::energy_hist(dtab(s), sid, e_max, nbins, s->st));
+        else HIPCHK(s, Launchers<double>::energy_hist(dtab(s), sid, e_max, nbins, s->st));
+    }
+    HIPCHK(s, hipMemcpyAsync(counts, s->h.hist, sizeof(unsigned long long) * (size_t)(nbins + 1),
+                             hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     return PIC_OK;
 }

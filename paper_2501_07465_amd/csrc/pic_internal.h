@@ -55,6 +55,7 @@ struct SpeciesDev {
     double qm;             // q / m
     double qw;             // q * weight
     double mw;             // m * weight
+    double mass;           // m
     double w2[3], gam[3];  // bound: omega_b^2, gamma_b
     double bw;             // bound: weight of the magnetic force
     double vf;             // Dirac: Fermi speed
@@ -126,6 +127,7 @@ struct SimDev {
     double* rho_a;         // [Lvol]
     double* rho_b;         // [Lvol]
     double* red;           // reduction scratch
+    unsigned long long* hist;  // [kMaxHistBins + 1] energy-histogram counts
     SpeciesDev sp[MAXSP];
 };
 
@@ -178,6 +180,8 @@ struct LoadArgs {
 
 // Launchers of the precision-templated kernels; explicitly instantiated for float (pic_k32.hip)
 // and double (pic_k64.hip).
+constexpr int kMaxHistBins = 4096;  // most bins of pic_energy_histogram
+
 template <typename R>
 struct Launchers {
     static hipError_t particles(int dims, const Launch& L);
@@ -185,6 +189,7 @@ struct Launchers {
     static hipError_t load(int dims, SimDev* dS, const LoadArgs& A, hipStream_t st);
     static hipError_t field_energy(const SimDev* dS, int par, double* part, int nb, hipStream_t st);
     static hipError_t kinetic(const SimDev* dS, int s, double* part, int nb, hipStream_t st);
+    static hipError_t energy_hist(const SimDev* dS, int s, double e_max, int nbins, hipStream_t st);
     static hipError_t rho(int dims, const SimDev* dS, double* rho, int nb, hipStream_t st);
     static hipError_t gauss(int dims, const SimDev* dS, int par, const double* rho, double* part, int nb, hipStream_t st);
     static hipError_t continuity(int dims, const SimDev* dS, double* part, int nb, hipStream_t st);

@@ -46,6 +46,7 @@ CLIGHT = 299792458.0
 EPS0 = 8.8541878128e-12
 HBAR = 1.054571817e-34
 EV = QE
+KB = 1.380649e-23
 
 
 def cfl_dt(dx: float, dims: int, frac: float = 0.95) -> float:
@@ -300,7 +301,26 @@ def eps_inv_map(w: dict):
     return out
 
 
-WORKLOADS = {"slab1d": slab1d, "disk2d": disk2d, "sphere3d": sphere3d, "sheet2d": sheet2d}
+# Fermi energies E_F = hbar^2 (3 pi^2 n)^(2/3) / (2 m_e) of the relaxation study's densities, stated
+# here as inputs (eV; the tests check them against the closed form).
+RELAX_EF_EV = {2e28: 2.6867273755, 4e28: 4.2649138622, 6e28: 5.5886181507}
+
+
+def relax3d(density=6e28, ppc=128, n=16, box_nm=2.0, temperature_ev=0.0375, t_end_fs=20.0, tile=(8, 8, 4)):
+    """The FD relaxation study (Sec. 2): a periodic 2 nm cube of bulk free electrons (fixed uniform
+    ions), random positions, Fermi-Dirac momenta at 0.0375 eV with mu = E_F of the density, run for
+    t_end_fs; the kinetic-energy tail is fitted to exp(-E / beta) along the run."""
+    dx = box_nm * 1e-9 / n
+    dt = cfl_dt(dx, 3)
+    return {"name": "relax3d", "dims": 3, "n": [n, n, n], "dx": [dx, dx, dx], "dt": dt,
+            "periodic": [1, 1, 1], "tile": list(tile), "sort_every": 20,
+            "species": [free_electrons(ppc, RELAX_EF_EV[density], temperature_ev * EV / KB,
+                                       density=density, reflect=False)],
+            "ion": "uniform", "steps": int(round(t_end_fs * 1e-15 / dt / 20.0)) * 20, "seed": 5,
+            "precision": "fp32", "relax": {"density": density, "temperature_ev": temperature_ev}}
+
+
+WORKLOADS = {"slab1d": slab1d, "disk2d": disk2d, "sphere3d": sphere3d, "sheet2d": sheet2d, "relax3d": relax3d}
 
 
 # ---------------------------------------------------------------------------------------------------
@@ -322,6 +342,8 @@ def small(name: str):
             sp["region"]["center"] = [20.2, 18.1, 21.7]
         w["source"]["index"] = [20, 18, 37]
         return w
+    if name == "relax3d":
+        return relax3d(ppc=8, n=8, box_nm=1.0, t_end_fs=0.5, tile=(4, 4, 4))
     if name == "sheet2d":
         return sheet2d(nx=100, ny=60, sheet_y=30, substrate=10, ppc_sheet=8, ppc_bound=4, steps=40,
                        tile=(16, 8), src_y=50)
