@@ -60,14 +60,21 @@ def sqrt_law(t, beta) -> float:
 def run_case(density: float, ppc: int, t_end_fs: float, samples: int = 20, nbins: int = 200, n: int = 16,
              log=None):
     """One study case on the device: beta(t) at `samples` times over t_end_fs, and A."""
-    from . import pic, workloads as W
+    from . import autotune, pic, workloads as W
     w = W.relax3d(density=density, ppc=ppc, n=n, t_end_fs=t_end_fs)
+    # the tile, block and unit tuned for the 16^3, 128 ppc cube (small tiles split into units: the
+    # cube has few cells for many particles)
+    tuned = autotune.shipped(W.relax3d(n=16, ppc=128), "fp32")
+    block = 256
+    if tuned is not None:
+        w = autotune.apply(w, tuned)
+        block = int(tuned["block"])
     sp = w["species"][0]
     ef = sp["e_fermi"]
     kt0 = w["relax"]["temperature_ev"] * QE
     e_max = ef + 40.0 * kt0
     e_lo = ef + 2.0 * kt0
-    sim = pic.Simulation(w, precision="fp32", graphs=True)
+    sim = pic.Simulation(w, precision="fp32", graphs=True, block=block, unit=w.get("unit", 0))
     per = max(20, (w["steps"] // samples) // 20 * 20)
     t, beta = [], []
     steps = 0
