@@ -15,11 +15,14 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortBlock = 1024;
 
-// keys[i] = tile-major key of particle i's cell (anchor cell for bound particles); vals[i] = i
+// keys[i] = tile-major key of particle i's cell (anchor cell for bound particles); vals[i] = i.
+// Block 0 also clears the digit totals the first histogram pass adds into.
 __global__ void k_keys(SimDev* __restrict__ S, int s)
 {
     const SpeciesDev& sp = S->sp[s];
     const int n = sp.n;
+    if (blockIdx.x == 0)
+        for (int d = threadIdx.x; d < 256; d += blockDim.x) S->sort_part[d] = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         int c[3];
         unpack_cell(*S, sp.cell[i], c);
@@ -28,8 +31,12 @@ __global__ void k_keys(SimDev* __restrict__ S, int s)
     }
 }
 
-// digit histogram per block: hist[d * nb + b]
-__global__ void __launch_bounds__(kSortBlock) k_radix_hist(SimDev* __restrict__ S, int s, int pass, int ipb)
+// digit histogram per block: hist[d * nb + b].  For sorts of at most kFuseBlocks blocks the digit
+// totals part[d] are summed here with one atomic per block and digit (part is zero on entry: cleared
+// by k_keys, then by each scatter pass); larger sorts form them in k_radix_rowsum.
+constexpr int kFuseBlocks = 1024;
+
+__global__ void __launch_bounds__(kSortBlock) k_radix_hist(SimDev* __restrict__ S, int s, int pass, int ipb, int fuse)
 {
     __shared__ int h[kRadix];
     const SpeciesDev& sp = S->sp[s];
@@ -46,11 +53,14 @@ __global__ void __launch_bounds__(kSortBlock) k_radix_hist(SimDev* __restrict__ 
     }
     __syncthreads();
     if (b < nb)
-        for (int d = threadIdx.x; d < kRadix; d += blockDim.x) S->sort_hist[d * nb + b] = h[d];
+        for (int d = threadIdx.x; d < kRadix; d += blockDim.x) {
+            S->sort_hist[d * nb + b] = h[d];
+            if (fuse && h[d]) atomicAdd(&S->sort_part[d], h[d]);
+        }
 }
 
-// Exclusive scan of hist[0 .. kRadix * nb) (digit-major) in two kernels with one block per digit:
-// the row sums, then each row scanned with its offset (the sum of the rows of lower digits).
+// Exclusive scan of hist[0 .. kRadix * nb) (digit-major), one block per digit: each row scanned with
+// its offset, the sum of the totals of the lower digits (the totals come from the histogram pass).
 constexpr int kScanThreads = 1024;
 
 // inclusive scan of v over the block (kScanThreads threads): DPP wavefront scans, then the wave
@@ -73,7 +83,8 @@ __device__ __forceinline__ int block_scan(int v, int* wsum, int* total)
     return carry + inc;
 }
 
-// part[d] = sum over blocks b of hist[d * nb + b]
+// part[d] = sum over blocks b of hist[d * nb + b] (sorts of many blocks: the histogram pass's
+// per-digit atomics would queue on 256 addresses)
 __global__ void __launch_bounds__(kScanThreads) k_radix_rowsum(SimDev* __restrict__ S, int s, int ipb)
 {
     __shared__ int wsum[kScanThreads / 64];
@@ -127,6 +138,9 @@ __global__ void __launch_bounds__(kSortBlock) k_radix_scatter(SimDev* __restrict
     const int nb = (n + ipb - 1) / ipb;
     const int b = blockIdx.x;
     if (b >= nb) return;
+    // the digit totals of this pass were consumed by the row scan: clear them for the next pass
+    if (b == 0)
+        for (int d = threadIdx.x; d < kRadix; d += blockDim.x) S->sort_part[d] = 0;
     const int shift = pass * kRadixBits;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nw = blockDim.x / 64;
@@ -333,8 +347,9 @@ hipError_t enqueue_sort(SimDev* dS, int s, int n, int passes, int elem, hipStrea
     if (n > 0) {
         hipLaunchKernelGGL(k_keys, dim3(g > 0 ? g : 1), dim3(256), 0, st, dS, s);
         for (int p = 0; p < passes; ++p) {
-            hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortBlock), 0, st, dS, s, p, ipb);
-            hipLaunchKernelGGL(k_radix_rowsum, dim3(kRadix), dim3(kScanThreads), 0, st, dS, s, ipb);
+            const int fuse = nb <= kFuseBlocks ? 1 : 0;
+            hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortBlock), 0, st, dS, s, p, ipb, fuse);
+            if (!fuse) hipLaunchKernelGGL(k_radix_rowsum, dim3(kRadix), dim3(kScanThreads), 0, st, dS, s, ipb);
             hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(kScanThreads), 0, st, dS, s, ipb);
             hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortBlock), 0, st, dS, s, p, ipb);
         }
