@@ -10,12 +10,18 @@ dominant kernel (the particle kernel) and for the whole step; a serving run (con
 of seeded uneven requests with Poisson arrivals, p50/p99 latency); the plain-C FP64 oracle timed
 on the host on a bounded sample (cpu_baseline).
 
+A dielectric leg runs the same workload with the metal's background permittivity (eps = 3.7 by
+default) inside the disk, as a per-cell inverse permittivity (eq:consteps), and reports its rate
+and its field kernel against the kernel without one.
+
 Algorithmic bytes (the minimum the method moves; no halos or re-reads):
   particle kernel, per launch: per particle its state read and written (FP32: 1D/2D/3D free
   40/48/56 B, 2D/3D bound 60/64 B, Dirac 48 B) + per occupied cell 24 B of E, B gathered and
   12 B of J written;
   whole step: particle kernel bytes + per cell 48 B (E, B read and written by the Yee update) +
-  per occupied cell 12 B (J read by the Yee update).
+  per occupied cell 12 B (J read by the Yee update);
+  dielectric field kernel, per launch: per cell 48 B of E, B + 12 B of inverse permittivity, per
+  occupied cell 12 B of J.
 achieved = bytes / average duration measured here with HIP events on the simulation's stream;
 peak = 8 TB/s HBM3E.  ``traffic`` is the kernel's measured HBM bytes per launch from committed
 rocprofv3 FETCH_SIZE/WRITE_SIZE runs (calibrated against a copy of known size) when those runs
@@ -181,6 +187,9 @@ def main():
     ap.add_argument("--block", type=int, default=None, help="particle-kernel block (default: tuned)")
     ap.add_argument("--unit", type=int, default=None, help="particles per work unit (default: tuned; 0 = tile)")
     ap.add_argument("--autotune", action="store_true", help="measure the tile/block/unit candidates now")
+    ap.add_argument("--eps-inf", type=float, default=3.7,
+                    help="background permittivity of the metal for the dielectric leg (0: skip it)")
+    ap.add_argument("--eps-steps", type=int, default=400)
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-scale", type=float, default=0.25)
     ap.add_argument("--serve-load", type=float, default=0.75)
@@ -277,11 +286,28 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": committed_traffic(args.workload, tile, block, w.get("unit", 0)),
-                     "kernel": f"k_particles<{w['dims']},float>", "bytes_per_launch": bytes_particle},
+                     "kernel": f"k_particles<{w['dims']},float,false,false>", "bytes_per_launch": bytes_particle},
         "step_roofline": {"bytes_per_step": bytes_step, "achieved": step_gbs, "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS},
         "field_energy_end": fe,
     }
+    if args.eps_inf > 0:
+        # the same workload with a per-cell inverse permittivity (the metal's background eps inside the
+        # first species' region): the dielectric variant of the field kernel reads 3 more values per node
+        we = W.with_dielectric(w, [args.eps_inf] * 3)
+        log(f"bench: dielectric leg, eps {args.eps_inf} in {we['dielectric']['region']['kind']}")
+        _, dte, kte, _ = run_gpu(we, "fp32", args.eps_steps, 20, graphs, args.time_kernels, block)
+        f_bytes = ncells * 12 * es + occ * 3 * es + ncells * 3 * es
+        f_ms = float(kte[1])
+        f_gbs = f_bytes / (f_ms * 1e-3) / 1e9
+        line["dielectric"] = {
+            "eps": [args.eps_inf] * 3, "region": we["dielectric"]["region"]["kind"], "steps": args.eps_steps,
+            "value": npart * args.eps_steps / dte, "unit": "particle-steps/s",
+            "ms_per_step": dte / args.eps_steps * 1e3,
+            "kernels_ms": {"particles": float(kte[0]), "fields": f_ms, "fields_without": float(kt[1])},
+            "field_roofline": {"bound": "hbm", "achieved": f_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": f_gbs / HBM_PEAK_GBS, "bytes_per_launch": f_bytes,
+                               "kernel": f"k_fields<{w['dims']},float,true>"}}
     if args.serve_requests > 0:
         line["serve"] = run_serve(args.serve_requests, args.serve_scale, args.serve_load, block,
                                   None, args.serve_budget_gib, args.serve_slots, log, w.get("unit", 0))

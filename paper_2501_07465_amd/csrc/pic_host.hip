@@ -524,7 +524,7 @@ static size_t plan(pic_sim* s, char* base, bool assign)
     long long nb = 1;
     for (auto& x : s->sp) nb = std::max(nb, (x.n + sort_ipb(x.n) - 1) / sort_ipb(x.n));
     h.sort_hist = P.take<int>((size_t)256 * nb);
-    h.sort_part = P.take<int>(256);
+    h.sort_part = P.take<int>(8 * 256);
     h.nspecies = (int)s->sp.size();
     for (size_t i = 0; i < s->sp.size(); ++i) {
         SpeciesHost& x = s->sp[i];

@@ -104,7 +104,7 @@ struct SimDev {
     int max_units;         // capacity of the unit list
     int unit_cap;          // most particles per unit (0: one unit per tile)
     int* sort_hist;        // radix-sort digit histogram scratch
-    int* sort_part;        // radix-sort digit totals [256]
+    int* sort_part;        // radix-sort digit totals [8][256] (copies summed by the row scan)
     void* J[2];            // [3][Lvol] J^{n+1/2} by step parity: every tile window's current is
                            // added by atomics, particles outside their window add directly
     int* fdirty;           // [2][nftiles] field tiles whose owned nodes of J[p] hold deposits

@@ -14,6 +14,9 @@ namespace pic {
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortBlock = 1024;
+// the fused digit totals are spread over kPartCopies copies (block b adds into copy b % copies) so
+// that fewer blocks queue on each address; the row scan sums the copies
+constexpr int kPartCopies = 8;
 
 // keys[i] = tile-major key of particle i's cell (anchor cell for bound particles); vals[i] = i.
 // Block 0 also clears the digit totals the first histogram pass adds into.
@@ -22,7 +25,7 @@ __global__ void k_keys(SimDev* __restrict__ S, int s)
     const SpeciesDev& sp = S->sp[s];
     const int n = sp.n;
     if (blockIdx.x == 0)
-        for (int d = threadIdx.x; d < 256; d += blockDim.x) S->sort_part[d] = 0;
+        for (int d = threadIdx.x; d < kPartCopies * kRadix; d += blockDim.x) S->sort_part[d] = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         int c[3];
         unpack_cell(*S, sp.cell[i], c);
@@ -55,7 +58,7 @@ __global__ void __launch_bounds__(kSortBlock) k_radix_hist(SimDev* __restrict__ 
     if (b < nb)
         for (int d = threadIdx.x; d < kRadix; d += blockDim.x) {
             S->sort_hist[d * nb + b] = h[d];
-            if (fuse && h[d]) atomicAdd(&S->sort_part[d], h[d]);
+            if (fuse && h[d]) atomicAdd(&S->sort_part[(b % kPartCopies) * kRadix + d], h[d]);
         }
 }
 
@@ -95,7 +98,7 @@ __global__ void __launch_bounds__(kScanThreads) k_radix_rowsum(SimDev* __restric
     for (int b = threadIdx.x; b < nb; b += kScanThreads) acc += row[b];
     int total;
     block_scan(acc, wsum, &total);
-    if (threadIdx.x == 0) S->sort_part[blockIdx.x] = total;
+    if (threadIdx.x == 0) S->sort_part[blockIdx.x] = total;  // copy 0; the other copies stay zero
 }
 
 // row d of hist replaced by its exclusive prefix in the digit-major order: thread t scans its
@@ -107,7 +110,10 @@ __global__ void __launch_bounds__(kScanThreads) k_radix_rowscan(SimDev* __restri
     const int nb = (n + ipb - 1) / ipb;
     const int d = blockIdx.x, tid = threadIdx.x;
     int total;
-    const int below = block_scan(tid < d ? S->sort_part[tid] : 0, wsum, &total);
+    int mine = 0;
+    if (tid < d)
+        for (int k = 0; k < kPartCopies; ++k) mine += S->sort_part[k * kRadix + tid];
+    const int below = block_scan(mine, wsum, &total);
     (void)below;
     const int offset = total;  // sum of the totals of digits 0 .. d-1
     int* row = S->sort_hist + (long long)d * nb;
@@ -140,7 +146,7 @@ __global__ void __launch_bounds__(kSortBlock) k_radix_scatter(SimDev* __restrict
     if (b >= nb) return;
     // the digit totals of this pass were consumed by the row scan: clear them for the next pass
     if (b == 0)
-        for (int d = threadIdx.x; d < kRadix; d += blockDim.x) S->sort_part[d] = 0;
+        for (int d = threadIdx.x; d < kPartCopies * kRadix; d += blockDim.x) S->sort_part[d] = 0;
     const int shift = pass * kRadixBits;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nw = blockDim.x / 64;
