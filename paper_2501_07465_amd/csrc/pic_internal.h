@@ -40,7 +40,7 @@ struct FieldTile;
 template <>
 struct FieldTile<1> { static constexpr int X = 256, Y = 1, Z = 1; };
 template <>
-struct FieldTile<2> { static constexpr int X = 61, Y = 6, Z = 1; };  // row-sweep task: 61 columns of a wavefront, 6 rows
+struct FieldTile<2> { static constexpr int X = 61, Y = 5, Z = 1; };  // row-sweep task: 61 columns of a wavefront, 5 rows
 template <>
 struct FieldTile<3> { static constexpr int X = 16, Y = 8, Z = 4; };
 
