@@ -214,6 +214,7 @@ static int setup_grid(pic_sim* s)
     h.nftiles = 1;
     for (int a = 0; a < 3; ++a) {
         h.FT[a] = a < g.dims ? ft[g.dims - 1][a] : 1;
+        if (g.dims == 2 && a == 1 && g.eps_cells) h.FT[a] = kSweepRowsEps;
         h.nft[a] = (g.n[a] + h.FT[a] - 1) / h.FT[a];
         h.nftiles *= h.nft[a];
         h.Lvol *= h.L[a];

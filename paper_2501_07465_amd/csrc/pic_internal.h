@@ -41,6 +41,9 @@ template <>
 struct FieldTile<1> { static constexpr int X = 256, Y = 1, Z = 1; };
 template <>
 struct FieldTile<2> { static constexpr int X = 61, Y = 5, Z = 1; };  // row-sweep task: 61 columns of a wavefront, 5 rows
+// rows of a row-sweep task in a simulation with a per-cell permittivity (its kernel keeps a deeper
+// load ring and is faster on taller tasks)
+constexpr int kSweepRowsEps = 6;
 template <>
 struct FieldTile<3> { static constexpr int X = 16, Y = 8, Z = 4; };
 
