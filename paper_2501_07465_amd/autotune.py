@@ -21,7 +21,7 @@ from . import pic
 
 TILES = {
     1: [(32,), (64,), (128,), (256,)],
-    2: [(8, 8), (16, 8), (16, 16), (32, 8), (32, 16), (64, 8), (32, 32)],
+    2: [(8, 8), (16, 8), (16, 16), (32, 8), (32, 16), (64, 8), (32, 32), (64, 16)],
     3: [(4, 4, 4), (8, 4, 4), (8, 8, 4), (16, 4, 4), (8, 8, 8)],
 }
 BLOCKS = (256, 512)

@@ -56,3 +56,32 @@ def test_fp32_dirac_speed_stays_at_fermi_speed():
         assert np.all(v[:, normal] == 0.0)
     print(f"FP32 Dirac |v| - v_F: {worst:.2f} machine epsilons of v_F", flush=True)
     assert worst <= 2.0
+
+
+@pytest.mark.parametrize("variant,steps,tol", [("dielectric", 400, 1e-3), ("barrier", 400, 1e-3),
+                                               ("diffuse", 400, 1e-2)])
+def test_fp32_run_with_next_row_physics(oracle, variant, steps, tol):
+    """The same whole-run check on the disk with a per-cell permittivity, a work-function barrier,
+    or diffusive walls.  Diffusive walls amplify the FP32/FP64 difference: a particle that reaches
+    the wall a step apart draws a different direction, so that run is held to 1e-2."""
+    from paper_2501_07465_amd import pic, workloads as W
+    w = W.small("disk2d")
+    if variant == "dielectric":
+        w = W.with_dielectric(w, [3.7, 3.7, 2.5])
+    elif variant == "barrier":
+        w = W.with_potential_wall(w, 9.8, 2.0)
+    else:
+        w = W.with_diffuse_walls(w)
+    print(f"case fp32 run disk {variant} {steps} steps", flush=True)
+    ref = oracle.build_workload(w)
+    sim = pic.Simulation(w, precision="fp32", states=ref.state(), fields=ref.fields(), graphs=True,
+                         series_cap=steps + 64)
+    sim.step(steps)
+    ref.step(steps)
+    u32, u64 = sim.field_energy(), ref.field_energy()
+    s32 = _spectrum(sim.current_series()[:steps])
+    s64 = _spectrum(ref.current_series()[:steps])
+    eu = abs(u32 - u64) / u64
+    es = float(np.max(np.abs(s32 - s64)) / np.max(s64))
+    print(f"fp32 disk {variant}: field energy rel {eu:.2e}, current spectrum rel {es:.2e}", flush=True)
+    assert eu <= tol and es <= tol, (variant, eu, es)

@@ -179,3 +179,27 @@ def test_diffuse_walls_refused_for_bound_species():
         pic.pic_init_species(h, pic.species_desc(sp), 1)
     assert e.value.code == pic.PIC_EINVAL
     pic.pic_destroy(h)
+
+
+def test_batch_mixes_diffuse_and_specular_members(oracle):
+    from paper_2501_07465_amd import pic, workloads as W
+    wa = _walls("disk2d")
+    wb = W.small("disk2d")
+    print("case batch diffuse + specular", flush=True)
+    base = oracle.build_workload(wa)
+    sta, fla = _toward_walls(wa, base.state()), base.fields()
+    refa = _oracle_from(oracle, wa, sta, fla)
+    refb = oracle.build_workload(wb)
+    batch = pic.Batch(2, 2, "fp64")
+    sa = pic.Simulation(wa, precision="fp64", states=sta, fields=fla, graphs=False, stream=batch.stream)
+    sb = pic.Simulation(wb, precision="fp64", states=refb.state(), fields=refb.fields(), graphs=False,
+                        stream=batch.stream)
+    batch.add(sa)
+    batch.add(sb)
+    batch.step(60)
+    refa.step(60)
+    refb.step(60)
+    batch.remove(sa)
+    batch.remove(sb)
+    _compare(sa, refa, wa, 1e-12, "batch diffuse")
+    _compare(sb, refb, wb, 1e-12, "batch specular")
