@@ -59,11 +59,12 @@ def test_fp32_dirac_speed_stays_at_fermi_speed():
 
 
 @pytest.mark.parametrize("variant,steps,tol", [("dielectric", 400, 1e-3), ("barrier", 400, 1e-3),
-                                               ("diffuse", 400, 1e-2)])
+                                               ("diffuse", 400, 1e-3)])
 def test_fp32_run_with_next_row_physics(oracle, variant, steps, tol):
     """The same whole-run check on the disk with a per-cell permittivity, a work-function barrier,
-    or diffusive walls.  Diffusive walls amplify the FP32/FP64 difference: a particle that reaches
-    the wall a step apart draws a different direction, so that run is held to 1e-2."""
+    or diffusive walls (measured 1e-6 .. 6e-6).  With diffusive walls a particle that reaches the
+    wall a step apart in FP32 would draw another direction; in 400 steps of the small disk that
+    does not move the collective quantities beyond the same bar."""
     from paper_2501_07465_amd import pic, workloads as W
     w = W.small("disk2d")
     if variant == "dielectric":
