@@ -49,7 +49,8 @@ class Species(C.Structure):
                 ("omega0_sq", C.c_double * 3), ("gamma", C.c_double * 3), ("b_weight", C.c_double),
                 ("v_f", C.c_double), ("sheet_normal", C.c_int), ("reflect", C.c_int),
                 ("region", C.c_int), ("rc", C.c_double * 3), ("rr", C.c_double),
-                ("rlo", C.c_double * 3), ("rhi", C.c_double * 3), ("seed", C.c_uint64)]
+                ("rlo", C.c_double * 3), ("rhi", C.c_double * 3), ("seed", C.c_uint64),
+                ("mass_per_particle", C.c_int)]
 
 
 class Init(C.Structure):
@@ -85,6 +86,7 @@ def lib():
         L.or_lambert.argtypes = [_D, _D, _D]
         L.or_scatter_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _D]
         L.or_fd_sample_speeds.argtypes = [C.c_double, C.c_double, C.c_double, C.c_size_t, _D, _D]
+        L.or_dirac_sample_energies.argtypes = [C.c_double, C.c_double, C.c_size_t, _D, _D]
         L.or_create.argtypes = [C.POINTER(Grid), C.POINTER(C.c_void_p)]
         L.or_destroy.argtypes = [C.c_void_p]
         L.or_add_species.argtypes = [C.c_void_p, C.POINTER(Species), C.c_size_t, _D, _D, _D]
@@ -199,6 +201,13 @@ def fd_speeds(e_fermi, kT, mass, u):
     return out
 
 
+def dirac_energies(ef, kT, u):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros_like(u)
+    lib().or_dirac_sample_energies(ef, kT, u.size, _dp(u), _dp(out))
+    return out
+
+
 def fermi_energy(n, m):
     return lib().or_fermi_energy(n, m)
 
@@ -239,6 +248,7 @@ def make_species(sp: dict, dims: int) -> Species:
     s.v_f = sp.get("v_f", 0.0)
     s.sheet_normal = sp.get("sheet_normal", -1)
     s.reflect = (2 if sp.get("scatter", "specular") == "diffuse" else 1) if sp.get("reflect", False) else 0
+    s.mass_per_particle = int(bool(sp.get("mass_per_particle", False)))
     reg = sp.get("region", {"kind": "all"})
     s.region = _REGION[reg["kind"]]
     for a in range(3):

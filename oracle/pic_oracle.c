@@ -157,7 +157,9 @@ typedef struct {
     double cdf[FD_NTAB + 1];
 } fd_table;
 
-static void fd_table_build(fd_table* t, double mu, double kT)
+/* dos2d = 0: the 3D free-carrier density of states sqrt(e), p(x) ~ x^2 f; dos2d = 1: the 2D Dirac
+ * density of states e, p(x) ~ x^3 f (de = 2 e_max x dx). */
+static void fd_table_build(fd_table* t, double mu, double kT, int dos2d)
 {
     t->e_max = mu + 40.0 * kT;
     double prev = 0.0; /* p(0) = 0 */
@@ -165,7 +167,7 @@ static void fd_table_build(fd_table* t, double mu, double kT)
     for (int k = 1; k <= FD_NTAB; ++k) {
         double x = (double)k / (double)FD_NTAB;
         double e = t->e_max * x * x;
-        double p = x * x / (1.0 + exp((e - mu) / kT));
+        double p = (dos2d ? x * x * x : x * x) / (1.0 + exp((e - mu) / kT));
         t->cdf[k] = t->cdf[k - 1] + 0.5 * (prev + p) * (1.0 / (double)FD_NTAB);
         prev = p;
     }
@@ -194,6 +196,28 @@ static double fd_speed(const fd_table* t, double e_fermi, double kT, double mass
     return sqrt(2.0 * e / mass);
 }
 
+/* Dirac carriers: energies under the 2D density of states, p(e) ~ e f(e)
+ * (Sec. 5 with eq:fddist; reading: the paper loads Dirac carriers at v_F
+ * without saying how their momenta are drawn).  At T = 0, e = E_F sqrt(u). */
+static double dirac_energy(const fd_table* t, double e_fermi, double kT, double u)
+{
+    if (kT > 0.0) return fd_table_energy(t, u);
+    return e_fermi * sqrt(u);
+}
+
+int or_dirac_sample_energies(double e_fermi, double kT, size_t n, const double* u, double* e)
+{
+    fd_table* t = NULL;
+    if (kT > 0.0) {
+        t = (fd_table*)malloc(sizeof(fd_table));
+        if (!t) return -2;
+        fd_table_build(t, e_fermi, kT, 1);
+    }
+    for (size_t i = 0; i < n; ++i) e[i] = dirac_energy(t, e_fermi, kT, u[i]);
+    free(t);
+    return 0;
+}
+
 int or_fd_sample_speeds(double e_fermi, double kT, double mass, size_t n,
                         const double* u, double* speed)
 {
@@ -201,7 +225,7 @@ int or_fd_sample_speeds(double e_fermi, double kT, double mass, size_t n,
     if (kT > 0.0) {
         t = (fd_table*)malloc(sizeof(fd_table));
         if (!t) return -1;
-        fd_table_build(t, e_fermi, kT);
+        fd_table_build(t, e_fermi, kT, 0);
     }
     for (size_t i = 0; i < n; ++i) speed[i] = fd_speed(t, e_fermi, kT, mass, u[i]);
     free(t);
@@ -573,6 +597,7 @@ static int check_species(const or_sim* s, const or_species* sp)
     if (sp->reflect < 0 || sp->reflect > 2) return -1;
     /* diffusive draws are three-dimensional: free carriers only */
     if (sp->reflect == 2 && sp->kind != OR_FREE) return -1;
+    if (sp->mass_per_particle && sp->kind != OR_DIRAC) return -1;
     if (sp->region == OR_REGION_BALL)
         for (int a = 1; a < s->g.dims; ++a)
             if (s->g.dx[a] != s->g.dx[0]) return -1;
@@ -624,8 +649,13 @@ int or_add_species(or_sim* s, const or_species* sp, size_t n,
     st->C = (long*)calloc(3 * (n ? n : 1), sizeof(long));
     st->O = (double*)calloc(3 * (n ? n : 1), sizeof(double));
     st->v = dup3(v, n, 1.0, 1.0, 1.0);
-    st->xi = dup3(sp->kind == OR_BOUND ? xi : NULL, n, 1.0, 1.0, 1.0);
+    /* bound: displacements; Dirac with per-particle mass: m_d in xi[i][0] */
+    int keep = sp->kind == OR_BOUND || (sp->kind == OR_DIRAC && sp->mass_per_particle);
+    st->xi = dup3(keep ? xi : NULL, n, 1.0, 1.0, 1.0);
     if (!st->C || !st->O || !st->v || !st->xi) return -2;
+    if (sp->kind == OR_DIRAC && sp->mass_per_particle)
+        for (size_t i = 0; i < n; ++i)
+            if (!(st->xi[3 * i] > 0.0)) return -1;
     for (size_t i = 0; i < n; ++i) {
         double X[3] = {0.0, 0.0, 0.0};
         for (int a = 0; a < s->g.dims; ++a) X[a] = x[3 * i + a] / s->g.dx[a];
@@ -711,10 +741,11 @@ int or_init_species(or_sim* s, const or_species* spin, const or_init* ini, int* 
 
     double kT = KB * ini->temperature;
     fd_table* tab = NULL;
-    if (sp.kind == OR_FREE && ini->momentum == OR_MOM_FD && kT > 0.0) {
+    const int dirac_mpp = sp.kind == OR_DIRAC && sp.mass_per_particle;
+    if (((sp.kind == OR_FREE && ini->momentum == OR_MOM_FD) || dirac_mpp) && kT > 0.0) {
         tab = (fd_table*)malloc(sizeof(fd_table));
         if (!tab) { free(cells); return -2; }
-        fd_table_build(tab, ini->e_fermi, kT);
+        fd_table_build(tab, ini->e_fermi, kT, sp.kind == OR_DIRAC);
     }
 
     for (size_t p = 0; p < n; ++p) {
@@ -752,6 +783,12 @@ int or_init_species(or_sim* s, const or_species* spin, const or_init* ini, int* 
             double ph = 2.0 * PI * u[3];
             v[e1] = sp.v_f * cos(ph);
             v[e2] = sp.v_f * sin(ph);
+            /* Sec. 5: transverse mass m_d = p / v_F of this carrier, p = e / v_F, with its
+             * energy e drawn from the 2D Fermi-Dirac distribution (u[4]) */
+            if (dirac_mpp) {
+                double e = dirac_energy(tab, ini->e_fermi, kT, u[4]);
+                st->xi[3 * p + 0] = e / (sp.v_f * sp.v_f);
+            }
         } else { /* bound */
             double r = ini->xi_radius * cbrt(u[3]);
             double ct = 2.0 * u[4] - 1.0;
@@ -1228,7 +1265,11 @@ static void particle_step(or_sim* s, double I[3])
             if (sp->kind == OR_FREE) or_push_free(qm, dt, E, B, v);
             else if (sp->kind == OR_BOUND)
                 or_push_bound(qm, dt, sp->omega0_sq, sp->gamma, sp->b_weight, E, B, xi, v);
-            else or_push_dirac(qm, dt, sp->v_f, sp->sheet_normal, E, B, v);
+            else {
+                /* Sec. 5: the per-particle transverse mass, when the species carries one */
+                double qmd = sp->mass_per_particle ? sp->q / xi[0] : qm;
+                or_push_dirac(qmd, dt, sp->v_f, sp->sheet_normal, E, B, v);
+            }
             /* x_{n+1} = x_n + dt v_{n+1/2} (eq:discrvel; xi_{n+1} = xi_n + dt v for bound particles) */
             for (int a = 0; a < d; ++a) x1[a] = x0[a] + dt * v[a] / s->g.dx[a];
             if (sp->kind == OR_BOUND) {

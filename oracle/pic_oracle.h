@@ -65,6 +65,8 @@ typedef struct {
     double rc[3], rr;    /* ball centre and radius [cells]                    */
     double rlo[3], rhi[3]; /* box corners [cells]                             */
     uint64_t seed;       /* Philox key of the diffusive draws                 */
+    int mass_per_particle; /* Dirac: 1 = transverse mass m_d = p / v_F per particle */
+                         /* (carried in xi[i][0]); 0 = the species mass m     */
 } or_species;
 
 typedef struct {
@@ -113,6 +115,8 @@ void or_lambert(const double n[3], const double u[2], double v[3]);
 void or_scatter_uniforms(uint64_t seed, uint32_t p, uint32_t step, uint32_t sid, double u[2]);
 int  or_fd_sample_speeds(double e_fermi, double kT, double mass, size_t n,
                          const double* u, double* speed);
+/* Energies of Dirac carriers (2D density of states ~ e) under eq:fddist. */
+int  or_dirac_sample_energies(double e_fermi, double kT, size_t n, const double* u, double* e);
 
 /* ---- simulation -------------------------------------------------------------- */
 int  or_create(const or_grid* g, or_sim** out);
