@@ -120,6 +120,9 @@ typedef struct {
     int region;          /* PIC_REGION_ALL, _BALL (rc, rr), _BOX (rlo, rhi); cell units  */
     double rc[3], rr;
     double rlo[3], rhi[3];
+    int mass_per_particle; /* Dirac, Sec. 5: 1 = transverse mass m_d = p / v_F per carrier,    */
+                         /* p = e / v_F with e drawn from the Fermi-Dirac distribution over the */
+                         /* 2D density of states at (e_fermi, temperature); 0 = the species m   */
 } pic_species_desc;
 
 typedef struct pic_sim pic_sim;
@@ -148,7 +151,8 @@ int pic_bind(pic_sim* s, void* dev_arena, size_t bytes, void* hip_stream);
 
 /* Copy a species' state in from host FP64 arrays: positions x[n][3] [m],
  * velocities v[n][3] (v_{n-1/2}) [m/s], and for bound species the anchor in x
- * and the displacement xi[n][3] [m] (may be NULL otherwise).  n must equal the
+ * and the displacement xi[n][3] [m]; for Dirac species with mass_per_particle
+ * xi[i][0] is carrier i's transverse mass m_d [kg] (> 0); NULL otherwise.  n must equal the
  * species count.  Positions are converted to (int32 cell, in-cell offset) on
  * the host.  Synchronous.  Errors: PIC_EINVAL, PIC_ESTATE, PIC_EDEVICE. */
 int pic_load_particles(pic_sim* s, int sid, const double* x, const double* v,
@@ -210,7 +214,8 @@ int pic_use_graphs(pic_sim* s, int on);
  *   PIC_DIAG_PARTICLE_COUNT     1 value per species
  *   PIC_DIAG_STEP               1 value: steps done
  *   PIC_DIAG_OVERFLOW           1 value: particles that left their tile window
- *   PIC_DIAG_EXPORT_PARTICLES   species arg: x[n][3], v[n][3], xi[n][3] (9n values)
+ *   PIC_DIAG_EXPORT_PARTICLES   species arg: x[n][3], v[n][3], xi[n][3] (9n values; Dirac
+ *                               species with mass_per_particle: m_d in xi[i][0])
  *   PIC_DIAG_EXPORT_FIELDS      e[3][L], b[3][L]
  *   PIC_DIAG_EXPORT_CURRENT     the last step's particle current J[3][L] (needs track_continuity)
  *   PIC_DIAG_KEYS               species arg: the cell key of each particle (as doubles)

@@ -350,7 +350,8 @@ class Sim:
         out = []
         for sid, sp in enumerate(self.species):
             x, v, xi = self.particles(sid)
-            out.append((x, v, xi if sp["kind"] == "bound" else None, self.weight(sid)))
+            keep = sp["kind"] == "bound" or (sp["kind"] == "dirac" and sp.get("mass_per_particle"))
+            out.append((x, v, xi if keep else None, self.weight(sid)))
         return out
 
     def particles(self, sid):

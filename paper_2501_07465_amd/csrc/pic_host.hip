@@ -332,6 +332,8 @@ extern "C" int pic_init_species(pic_sim* s, const pic_species_desc* d, uint64_t 
     if (d->region < PIC_REGION_ALL || d->region > PIC_REGION_BOX) return fail(s, PIC_EINVAL, "region");
     if (d->reflect < 0 || d->reflect > 2) return fail(s, PIC_EINVAL, "reflect must be 0, 1 or 2");
     if (d->reflect == 2 && d->kind != PIC_FREE) return fail(s, PIC_EINVAL, "diffusive walls are for free species");
+    if (d->mass_per_particle != 0 && d->mass_per_particle != 1) return fail(s, PIC_EINVAL, "mass_per_particle must be 0 or 1");
+    if (d->mass_per_particle && d->kind != PIC_DIRAC) return fail(s, PIC_EINVAL, "per-particle mass is for Dirac species");
     if (d->region == PIC_REGION_BALL)
         for (int a = 1; a < dims; ++a)
             if (s->g.dx[a] != s->g.dx[0]) return fail(s, PIC_EINVAL, "ball regions need equal cell sizes");
@@ -386,8 +388,10 @@ extern "C" int pic_init_species(pic_sim* s, const pic_species_desc* d, uint64_t 
         double dv = 1.0;
         for (int a = 0; a < dims; ++a) dv *= s->g.dx[a];
         x.weight = dens * dv / d->ppc;
-        if (d->kind == PIC_FREE && d->momentum == PIC_MOM_FD && d->temperature > 0.0) {
-            // inverse-CDF table of eq:fddist on x = sqrt(e/e_max), e_max = mu + 40 kT
+        const bool dmpp = d->kind == PIC_DIRAC && d->mass_per_particle;
+        if (((d->kind == PIC_FREE && d->momentum == PIC_MOM_FD) || dmpp) && d->temperature > 0.0) {
+            // inverse-CDF table of eq:fddist on x = sqrt(e/e_max), e_max = mu + 40 kT; the density of
+            // states is sqrt(e) for free carriers (weight x^2) and e for Dirac carriers (x^3)
             const double mu = d->e_fermi, kT = kKb * d->temperature;
             x.e_max = mu + 40.0 * kT;
             x.cdf.resize(kFdTab + 1);
@@ -396,7 +400,7 @@ extern "C" int pic_init_species(pic_sim* s, const pic_species_desc* d, uint64_t 
             for (int k = 1; k <= kFdTab; ++k) {
                 const double xx = (double)k / (double)kFdTab;
                 const double e = x.e_max * xx * xx;
-                const double p = xx * xx / (1.0 + std::exp((e - mu) / kT));
+                const double p = (dmpp ? xx * xx * xx : xx * xx) / (1.0 + std::exp((e - mu) / kT));
                 x.cdf[k] = x.cdf[k - 1] + 0.5 * (prev + p) * (1.0 / (double)kFdTab);
                 prev = p;
             }
@@ -537,7 +541,9 @@ static size_t plan(pic_sim* s, char* base, bool assign)
             for (int a = 0; a < 3; ++a) {
                 x.off[k][a] = a < s->g.dims ? P.takeb(n * es) : nullptr;
                 x.v[k][a] = P.takeb(n * es);
-                x.xi[k][a] = bound ? P.takeb(n * es) : nullptr;
+                // bound: displacements; Dirac with per-carrier mass: q / m_d in xi[0]
+                const bool dm = x.d.kind == PIC_DIRAC && x.d.mass_per_particle && a == 0;
+                x.xi[k][a] = (bound || dm) ? P.takeb(n * es) : nullptr;
             }
         }
         d.keys = P.take<int>(n);
@@ -568,6 +574,8 @@ static void mirror_species(pic_sim* s, int i)
     d.qw = D.q * x.weight;
     d.mw = x.mass * x.weight;
     d.mass = x.mass;
+    d.q = D.q;
+    d.mpp = (D.kind == PIC_DIRAC && D.mass_per_particle) ? 1 : 0;
     for (int a = 0; a < 3; ++a) {
         d.w2[a] = D.kind == PIC_BOUND ? D.omega0[a] * D.omega0[a] : 0.0;
         d.gam[a] = D.kind == PIC_BOUND ? D.gamma[a] : 0.0;
@@ -621,7 +629,8 @@ static hipError_t launch_load(pic_sim* s, int i)
     A.ntab = kFdTab;
     A.seed = x.seed;
     A.e_fermi = x.d.e_fermi;
-    A.kT = (x.d.kind == PIC_FREE && x.d.momentum == PIC_MOM_FD) ? kKb * x.d.temperature : 0.0;
+    A.kT = ((x.d.kind == PIC_FREE && x.d.momentum == PIC_MOM_FD) || (x.d.kind == PIC_DIRAC && x.d.mass_per_particle))
+               ? kKb * x.d.temperature : 0.0;
     A.mass = x.mass;
     A.pert_amp = x.d.pert_amp;
     A.xi_radius = x.d.xi_radius;
@@ -709,10 +718,12 @@ extern "C" int pic_load_particles(pic_sim* s, int sid, const double* x, const do
     if (!x || !v) return fail(s, PIC_EINVAL, "null x or v");
     const bool bound = sp.d.kind == PIC_BOUND;
     if (bound && !xi) return fail(s, PIC_EINVAL, "bound species need xi");
+    const bool dmpp = sp.d.kind == PIC_DIRAC && sp.d.mass_per_particle;
+    if (dmpp && !xi) return fail(s, PIC_EINVAL, "per-carrier Dirac masses need xi[i][0]");
     const int dims = s->g.dims;
     std::vector<int> cell(n);
     std::vector<double> off[3], vv[3], xx[3];
-    for (int a = 0; a < 3; ++a) { off[a].resize(n); vv[a].resize(n); xx[a].resize(bound ? n : 0); }
+    for (int a = 0; a < 3; ++a) { off[a].resize(n); vv[a].resize(n); xx[a].resize(bound || (dmpp && a == 0) ? n : 0); }
     for (size_t i = 0; i < n; ++i) {
         int c[3] = {0, 0, 0};
         for (int a = 0; a < 3; ++a) {
@@ -736,6 +747,11 @@ extern "C" int pic_load_particles(pic_sim* s, int sid, const double* x, const do
             off[a][i] = o;
         }
         cell[i] = pack_cell(s->h, c[0], c[1], c[2]);
+        if (dmpp) {
+            const double m = xi[3 * i];
+            if (!(m > 0.0) || !std::isfinite(m)) return fail(s, PIC_EINVAL, "Dirac mass of particle %zu must be positive", i);
+            xx[0][i] = sp.d.q / m;  // stored as q / m_d
+        }
     }
     const int p = sp.parity;
     HIPCHK(s, hipMemcpyAsync(sp.cell[p], cell.data(), n * sizeof(int), hipMemcpyHostToDevice, s->st));
@@ -749,7 +765,7 @@ extern "C" int pic_load_particles(pic_sim* s, int sid, const double* x, const do
     for (int a = 0; a < 3; ++a) {
         if (a < dims) HIPCHK(s, put(sp.off[p][a], off[a]));
         HIPCHK(s, put(sp.v[p][a], vv[a]));
-        if (bound) HIPCHK(s, put(sp.xi[p][a], xx[a]));
+        if (bound || (dmpp && a == 0)) HIPCHK(s, put(sp.xi[p][a], xx[a]));
     }
     HIPCHK(s, hipStreamSynchronize(s->st));
     s->need_sort = true;
@@ -1199,6 +1215,10 @@ extern "C" int pic_diag(pic_sim* s, int kind, int arg, double* out, size_t cap, 
             if (a < s->g.dims && (r = fetch_real(s, x.off[p][a], n, X + a, 3))) return r;
             if ((r = fetch_real(s, x.v[p][a], n, V + a, 3))) return r;
             if (x.d.kind == PIC_BOUND && (r = fetch_real(s, x.xi[p][a], n, XI + a, 3))) return r;
+        }
+        if (x.d.kind == PIC_DIRAC && x.d.mass_per_particle) {
+            if ((r = fetch_real(s, x.xi[p][0], n, XI, 3))) return r;
+            for (size_t i = 0; i < n; ++i) XI[3 * i] = x.d.q / XI[3 * i];  // stored q / m_d -> m_d
         }
         for (size_t i = 0; i < n; ++i) {
             int c[3];

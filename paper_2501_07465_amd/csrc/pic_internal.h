@@ -59,6 +59,8 @@ struct SpeciesDev {
     double qw;             // q * weight
     double mw;             // m * weight
     double mass;           // m
+    double q;              // charge
+    int mpp;               // Dirac: per-carrier q / m_d in xi[0]
     double w2[3], gam[3];  // bound: omega_b^2, gamma_b
     double bw;             // bound: weight of the magnetic force
     double vf;             // Dirac: Fermi speed

@@ -215,6 +215,8 @@ __global__ void k_permute(SimDev* __restrict__ S, int s, int passes, int elem)
             if (bound)
                 for (int a = 0; a < 3; ++a)
                     reinterpret_cast<float*>(sp.xi_alt[a])[i] = reinterpret_cast<const float*>(sp.xi[a])[j];
+            else if (sp.mpp)
+                reinterpret_cast<float*>(sp.xi_alt[0])[i] = reinterpret_cast<const float*>(sp.xi[0])[j];
         } else {
             for (int a = 0; a < dims; ++a)
                 reinterpret_cast<double*>(sp.off_alt[a])[i] = reinterpret_cast<const double*>(sp.off[a])[j];
@@ -223,6 +225,8 @@ __global__ void k_permute(SimDev* __restrict__ S, int s, int passes, int elem)
             if (bound)
                 for (int a = 0; a < 3; ++a)
                     reinterpret_cast<double*>(sp.xi_alt[a])[i] = reinterpret_cast<const double*>(sp.xi[a])[j];
+            else if (sp.mpp)
+                reinterpret_cast<double*>(sp.xi_alt[0])[i] = reinterpret_cast<const double*>(sp.xi[0])[j];
         }
     }
 }

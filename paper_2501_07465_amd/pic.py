@@ -56,7 +56,8 @@ class SpeciesDesc(C.Structure):
                 ("pert_amp", C.c_double), ("pert_mode", C.c_int), ("omega0", C.c_double * 3),
                 ("gamma", C.c_double * 3), ("b_weight", C.c_double), ("xi_radius", C.c_double),
                 ("v_f", C.c_double), ("sheet_normal", C.c_int), ("reflect", C.c_int), ("region", C.c_int),
-                ("rc", C.c_double * 3), ("rr", C.c_double), ("rlo", C.c_double * 3), ("rhi", C.c_double * 3)]
+                ("rc", C.c_double * 3), ("rr", C.c_double), ("rlo", C.c_double * 3), ("rhi", C.c_double * 3),
+                ("mass_per_particle", C.c_int)]
 
 
 _lib = None
@@ -326,6 +327,7 @@ def species_desc(sp: dict, count: int = 0, weight: float = 0.0) -> SpeciesDesc:
     d.v_f = sp.get("v_f", 0.0)
     d.sheet_normal = sp.get("sheet_normal", -1)
     d.reflect = (2 if sp.get("scatter", "specular") == "diffuse" else 1) if sp.get("reflect", False) else 0
+    d.mass_per_particle = int(bool(sp.get("mass_per_particle", False)))
     reg = sp.get("region", {"kind": "all"})
     d.region = _REGION[reg["kind"]]
     for a in range(3):
