@@ -887,10 +887,11 @@ static int enqueue_sort_all(pic_sim* s, std::vector<int>* sorted)
     return PIC_OK;
 }
 
-static bool has_diffuse(const pic_sim* s)
+// species options whose code lives only in the RARE particle kernels
+static bool has_rare(const pic_sim* s)
 {
     for (const auto& x : s->sp)
-        if (x.d.reflect == 2) return true;
+        if (x.d.reflect == 2 || (x.d.kind == PIC_DIRAC && x.d.mass_per_particle)) return true;
     return false;
 }
 
@@ -905,7 +906,7 @@ static Launch make_launch(pic_sim* s)
     L.block = s->g.block;
     L.ftiles_total = s->h.nftiles;
     L.eps = s->h.einv != nullptr;
-    L.diffuse = has_diffuse(s);
+    L.rare = has_rare(s);
     L.ext = s->h.eext != nullptr;
     L.stream = s->st;
     return L;
@@ -1371,7 +1372,7 @@ static int batch_enqueue_period(pic_batch* b, std::vector<std::vector<int>>* sor
 {
     const int n = (int)b->members.size();
     int max_vf = 1, max_vj = 1, lds = 1, pgrid = 1, ft = 0, block = 64;
-    bool eps = false, diffuse = false, ext = false;
+    bool eps = false, rare = false, ext = false;
     for (int i = 0; i < n; ++i) {
         pic_sim* s = b->members[i];
         std::vector<int> mine;
@@ -1389,7 +1390,7 @@ static int batch_enqueue_period(pic_batch* b, std::vector<std::vector<int>>* sor
         ft += s->h.nftiles;
         block = std::max(block, s->g.block);
         eps = eps || s->h.einv != nullptr;
-        diffuse = diffuse || has_diffuse(s);
+        rare = rare || has_rare(s);
         ext = ext || s->h.eext != nullptr;
     }
     Launch L{};
@@ -1401,7 +1402,7 @@ static int batch_enqueue_period(pic_batch* b, std::vector<std::vector<int>>* sor
     L.block = block;
     L.ftiles_total = ft;
     L.eps = eps;
-    L.diffuse = diffuse;
+    L.rare = rare;
     L.ext = ext;
     L.stream = b->st;
     const int P = b->members[0]->g.sort_every;

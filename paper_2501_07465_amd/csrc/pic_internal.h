@@ -170,7 +170,7 @@ struct Launch {
     int block;             // particle-kernel block
     int ftiles_total;      // field tiles over members
     bool eps;              // some member has a per-cell inverse permittivity
-    bool diffuse;          // some member has a species with diffusive walls
+    bool rare;             // some member has a species with diffusive walls or per-carrier Dirac mass
     bool ext;              // some member has a static external field
     hipStream_t stream;
 };
