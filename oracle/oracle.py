@@ -84,6 +84,7 @@ def lib():
         L.or_gyro_matrix.argtypes = [_D, _D, _D]
         L.or_reflect.argtypes = [C.POINTER(Species), C.c_int, _D, _D]
         L.or_lambert.argtypes = [_D, _D, _D]
+        L.or_lambert2d.argtypes = [_D, C.c_int, _D, _D]
         L.or_scatter_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _D]
         L.or_fd_sample_speeds.argtypes = [C.c_double, C.c_double, C.c_double, C.c_size_t, _D, _D]
         L.or_dirac_sample_energies.argtypes = [C.c_double, C.c_double, C.c_size_t, _D, _D]
@@ -161,6 +162,12 @@ def push_dirac(qm, dt, v_f, normal, E, B, v):
 def lambert(n, u, v):
     n = _v3(n); u = np.ascontiguousarray(u, dtype=np.float64); v = _v3(v).copy()
     lib().or_lambert(_dp(n), _dp(u), _dp(v))
+    return v
+
+
+def lambert2d(n, normal, u, v):
+    n = _v3(n); u = np.ascontiguousarray(u, dtype=np.float64); v = _v3(v).copy()
+    lib().or_lambert2d(_dp(n), normal, _dp(u), _dp(v))
     return v
 
 

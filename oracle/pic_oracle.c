@@ -437,6 +437,20 @@ void or_lambert(const double n[3], const double u[2], double v[3])
     for (int a = 0; a < 3; ++a) v[a] = speed * (ct * n[a] + st * (cp * t1[a] + sp * t2[a]));
 }
 
+/* Dirac carriers move in their sheet, so their diffusive draw is two-dimensional.  Reading: the
+ * in-sheet cosine law, sin(theta) = 2 u0 - 1 (uniform), about the in-sheet inward normal n
+ * (n has no component along the sheet normal axis `normal`), with the tangent t = e_normal x n;
+ * the speed (v_F) is kept. */
+void or_lambert2d(const double n[3], int normal, const double u[2], double v[3])
+{
+    double speed = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    double e[3] = {0.0, 0.0, 0.0};
+    e[normal] = 1.0;
+    double t[3] = {e[1] * n[2] - e[2] * n[1], e[2] * n[0] - e[0] * n[2], e[0] * n[1] - e[1] * n[0]};
+    double st = 2.0 * u[0] - 1.0, ct = sqrt(1.0 - st * st);
+    for (int a = 0; a < 3; ++a) v[a] = speed * (ct * n[a] + st * t[a]);
+}
+
 void or_scatter_uniforms(uint64_t seed, uint32_t p, uint32_t step, uint32_t sid, double u[2])
 {
     uint32_t ctr[4] = {p, step, sid, 0x80000000u};
@@ -595,8 +609,8 @@ static int check_species(const or_sim* s, const or_species* sp)
 {
     if (sp->kind < OR_FREE || sp->kind > OR_DIRAC || sp->m <= 0.0) return -1;
     if (sp->reflect < 0 || sp->reflect > 2) return -1;
-    /* diffusive draws are three-dimensional: free carriers only */
-    if (sp->reflect == 2 && sp->kind != OR_FREE) return -1;
+    /* diffusive draws: free carriers (3D) and Dirac carriers with a sheet normal (in-sheet) */
+    if (sp->reflect == 2 && !(sp->kind == OR_FREE || (sp->kind == OR_DIRAC && sp->sheet_normal >= 0))) return -1;
     if (sp->mass_per_particle && sp->kind != OR_DIRAC) return -1;
     if (sp->region == OR_REGION_BALL)
         for (int a = 1; a < s->g.dims; ++a)
@@ -1284,7 +1298,19 @@ static void particle_step(or_sim* s, double I[3])
                     if (sp->reflect == 2) {
                         double u[2];
                         or_scatter_uniforms(sp->seed, (uint32_t)p, (uint32_t)s->step, (uint32_t)isp, u);
-                        or_lambert(n, u, v);
+                        if (sp->kind == OR_DIRAC) {
+                            /* the in-sheet part of the normal, renormalised; where it vanishes
+                             * (a crossing along the sheet normal, which an in-sheet carrier does
+                             * not make) the specular result stands */
+                            n[sp->sheet_normal] = 0.0;
+                            double l = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+                            if (l > 0.0) {
+                                for (int a = 0; a < 3; ++a) n[a] /= l;
+                                or_lambert2d(n, sp->sheet_normal, u, v);
+                            }
+                        } else {
+                            or_lambert(n, u, v);
+                        }
                     }
                 }
             }

@@ -110,6 +110,9 @@ int  or_reflect(const or_species* s, int dims, double X[3], double v[3]);
  * drawn from the cosine (Lambert) law about the inward unit normal n, with the
  * two uniforms u[0], u[1] in (0,1). */
 void or_lambert(const double n[3], const double u[2], double v[3]);
+/* Dirac carriers: the in-sheet cosine law, sin(theta) = 2 u[0] - 1, about the
+ * in-sheet inward normal n, tangent e_normal x n; the speed kept. */
+void or_lambert2d(const double n[3], int normal, const double u[2], double v[3]);
 /* The two uniforms of the diffusive draw of particle p of species sid in step
  * `step` (Philox4x32-10, counter (p, step, sid, 0x80000000), key seed). */
 void or_scatter_uniforms(uint64_t seed, uint32_t p, uint32_t step, uint32_t sid, double u[2]);

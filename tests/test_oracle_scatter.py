@@ -10,7 +10,7 @@ from the cosine (Lambert) law about the inward normal at the escaped point).
 * In a run, every particle that crossed the wall keeps its speed and leaves with d.n > 0; the
   others are untouched; particles stay in the region; diffuse walls randomise the direction of a
   beam that specular walls keep ordered.
-* Diffusive scattering is refused for bound and Dirac species.
+* Diffusive scattering is refused for bound species and for Dirac species without a sheet.
 """
 import math
 import os
@@ -175,11 +175,11 @@ def test_walls_confine_and_diffuse_walls_randomise_a_beam(oracle, scatter):
         assert abs(np.mean(v1[:, 0])) < 0.2 * speed
 
 
-def test_diffuse_refused_for_bound_and_dirac(oracle):
+def test_diffuse_refused_for_bound_and_sheetless_dirac(oracle):
     w, sp = _disk_world("diffuse")
     s = oracle.Sim(w)
     for kind, extra in (("bound", {"omega0": [1e15] * 3, "gamma": [1e13] * 3}),
-                        ("dirac", {"v_f": 1e6, "sheet_normal": 1, "m": 1e-32})):
+                        ("dirac", {"v_f": 1e6, "sheet_normal": -1, "m": 1e-32})):
         bad = dict(sp, kind=kind, **extra)
         with pytest.raises(RuntimeError):
             s.add_species(bad, 1.0, np.array([[16e-9, 16e-9, 0.0]]), np.array([[1e5, 0.0, 0.0]]),
