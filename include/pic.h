@@ -115,8 +115,9 @@ typedef struct {
     int sheet_normal;    /* Dirac: axis normal to the sheet (velocity component removed) */
     int reflect;         /* at the region boundary (Sec. 3): 0 none, 1 specular, 2 diffusive: */
                          /* the position mirrored, the speed kept and the direction drawn     */
-                         /* from the cosine law about the inward normal (free species only;   */
-                         /* Philox4x32-10 counter (index, step, species id, 2^31), key seed)  */
+                         /* from the cosine law about the inward normal (free species; Dirac  */
+                         /* sheets in the sheet plane, sin(theta) = 2u - 1; Philox4x32-10     */
+                         /* counter (index, step, species id, 2^31), key seed)                */
     int region;          /* PIC_REGION_ALL, _BALL (rc, rr), _BOX (rlo, rhi); cell units  */
     double rc[3], rr;
     double rlo[3], rhi[3];

@@ -331,7 +331,8 @@ extern "C" int pic_init_species(pic_sim* s, const pic_species_desc* d, uint64_t 
     if (!(d->q != 0.0) || !std::isfinite(d->q)) return fail(s, PIC_EINVAL, "charge");
     if (d->region < PIC_REGION_ALL || d->region > PIC_REGION_BOX) return fail(s, PIC_EINVAL, "region");
     if (d->reflect < 0 || d->reflect > 2) return fail(s, PIC_EINVAL, "reflect must be 0, 1 or 2");
-    if (d->reflect == 2 && d->kind != PIC_FREE) return fail(s, PIC_EINVAL, "diffusive walls are for free species");
+    if (d->reflect == 2 && !(d->kind == PIC_FREE || (d->kind == PIC_DIRAC && d->sheet_normal >= 0)))
+        return fail(s, PIC_EINVAL, "diffusive walls are for free species and Dirac sheets");
     if (d->mass_per_particle != 0 && d->mass_per_particle != 1) return fail(s, PIC_EINVAL, "mass_per_particle must be 0 or 1");
     if (d->mass_per_particle && d->kind != PIC_DIRAC) return fail(s, PIC_EINVAL, "per-particle mass is for Dirac species");
     if (d->region == PIC_REGION_BALL)
