@@ -104,6 +104,7 @@ def lib():
         L.or_get_fields.argtypes = [C.c_void_p, _D, _D]
         L.or_set_fields.argtypes = [C.c_void_p, _D, _D]
         L.or_set_eps_inv.argtypes = [C.c_void_p, _D]
+        L.or_set_eps_offdiag.argtypes = [C.c_void_p, _D]
         L.or_set_ext_field.argtypes = [C.c_void_p, _D]
         L.or_energy_histogram.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int, C.POINTER(C.c_uint64)]
         L.or_get_current.argtypes = [C.c_void_p, _D]
@@ -421,6 +422,17 @@ class Sim:
         if rc != 0:
             raise ValueError("or_set_eps_inv failed (%d)" % rc)
 
+    def set_eps_offdiag(self, eoff):
+        """Off-diagonal inverse permittivity eoff[6][L] (row a, column b != a at the E_a node, order
+        01 02 10 12 20 21; eq:consteps with a full tensor); None removes it."""
+        if eoff is None:
+            rc = lib().or_set_eps_offdiag(self.h, None)
+        else:
+            eoff = np.ascontiguousarray(eoff, dtype=np.float64).ravel()
+            rc = lib().or_set_eps_offdiag(self.h, _dp(eoff))
+        if rc != 0:
+            raise ValueError("or_set_eps_offdiag failed (%d)" % rc)
+
     def current(self):
         n = lib().or_field_len(self.h)
         j = np.zeros(3 * n)
@@ -500,6 +512,9 @@ def build_workload(w: dict, seed: int | None = None) -> Sim:
         from paper_2501_07465_amd import workloads as W
         if w.get("dielectric") is not None:
             s.set_eps_inv(W.eps_inv_map(w))
+            off = W.eps_offdiag_map(w)
+            if off is not None:
+                s.set_eps_offdiag(off)
         if w.get("wall") is not None:
             s.set_ext_field(W.wall_field(w))
     s.set_ion_background(w.get("ion", "local") == "uniform")

@@ -505,6 +505,8 @@ struct or_sim {
     double* B[3];
     double* J[3];    /* particle current of the last step, J^{n+1/2}         */
     double* einv[3]; /* inverse permittivity at the E_c nodes (NULL: unit)   */
+    double* eoff[6]; /* off-diagonal inverse permittivity (a, b), a != b, at */
+                     /* the E_a nodes, order 01 02 10 12 20 21 (NULL: none)  */
     double* eext[3]; /* static external field at the E_c nodes (NULL: none)  */
     double* rho_ion; /* fixed background charge density at nodes            */
     int have_ion;
@@ -599,6 +601,7 @@ void or_destroy(or_sim* s)
     for (int c = 0; c < 3; ++c) {
         free(s->E[c]); free(s->B[c]); free(s->J[c]); free(s->einv[c]); free(s->eext[c]);
     }
+    for (int m = 0; m < 6; ++m) free(s->eoff[m]);
     free(s->rho_ion);
     for (int i = 0; i < s->nsp; ++i) { free(s->sp[i].C); free(s->sp[i].O); free(s->sp[i].v); free(s->sp[i].xi); }
     free(s->series);
@@ -1173,15 +1176,42 @@ static int source_hits(const or_sim* s, int c, const long ijk[3])
     return 1;
 }
 
+/* Off-diagonal slot of the pair (a, b), a != b: order 01 02 10 12 20 21. */
+static int off_slot(int a, int b) { return 2 * a + (b > a ? b - 1 : b); }
+
+/* The mean of U_b over the E_b nodes nearest to the E_a node ijk.  The two
+ * sit half a cell apart along a and along b (E_a is half-integer along a,
+ * E_b along b), so the nearest E_b nodes are ijk + s e_a - t e_b with s, t in
+ * {0, 1} on the active axes: four in 2D and 3D when both axes are active, two
+ * when one is, one when neither is. */
+static double mean_nearest(const or_sim* s, const double* Ub, int a, int b, const long ijk[3])
+{
+    int ns = active(s, a) ? 2 : 1, nt = active(s, b) ? 2 : 1;
+    double sum = 0.0;
+    for (int sa = 0; sa < ns; ++sa)
+        for (int tb = 0; tb < nt; ++tb) {
+            long h[3] = {ijk[0], ijk[1], ijk[2]};
+            h[a] += sa;
+            h[b] -= tb;
+            sum += Ub[fidx(s, h[0], h[1], h[2])];
+        }
+    return sum / (double)(ns * nt);
+}
+
 static void e_step(or_sim* s, double t_half)
 {
     double dt = s->g.dt, c2 = CLIGHT * CLIGHT;
     double jsrc = source_value(s, t_half);
     double* Eold[3];
     double* Emid[3];
+    double* U[3] = {NULL, NULL, NULL};
+    int tensor = 0;
+    for (int m = 0; m < 6; ++m)
+        if (s->eoff[m]) tensor = 1;
     for (int c = 0; c < 3; ++c) {
         Eold[c] = (double*)malloc(sizeof(double) * s->len);
         memcpy(Eold[c], s->E[c], sizeof(double) * s->len);
+        if (tensor) U[c] = (double*)calloc(s->len, sizeof(double));
     }
     for (int c = 0; c < 3; ++c) {
         int half[3];
@@ -1196,11 +1226,40 @@ static void e_step(or_sim* s, double t_half)
                     double curl = dbwd(s, s->B[a2], i, j, k, a1) - dbwd(s, s->B[a1], i, j, k, a2);
                     double jc = s->J[c][fidx(s, i, j, k)] + (source_hits(s, c, ijk) ? jsrc : 0.0);
                     /* eq:consteps: the curl and current terms are scaled by the inverse
-                     * dielectric tensor, here diagonal and taken at the E_c node */
+                     * dielectric tensor; its diagonal entry is taken at the E_c node */
                     double ei = s->einv[c] ? s->einv[c][fidx(s, i, j, k)] : 1.0;
-                    s->E[c][fidx(s, i, j, k)] += dt * ei * (c2 * curl - jc / EPS0);
+                    double u = c2 * curl - jc / EPS0;
+                    if (tensor) U[c][fidx(s, i, j, k)] = u;
+                    s->E[c][fidx(s, i, j, k)] += dt * ei * u;
                 }
     }
+    /* eq:consteps with a full tensor: row a of the inverse tensor at the E_a node
+     * multiplies the update vector, whose other components live on their own
+     * nodes and are averaged onto the E_a node (mean_nearest).  Off-diagonal
+     * entries are nonzero only two nodes or more inside every open face, so the
+     * averaged nodes are interior nodes with a computed U. */
+    if (tensor)
+        for (int a = 0; a < 3; ++a) {
+            int half[3];
+            stag_E(a, half);
+            int n0 = valid_len(s, 0, half[0]), n1 = valid_len(s, 1, half[1]), n2 = valid_len(s, 2, half[2]);
+            for (long k = 0; k < n2; ++k)
+                for (long j = 0; j < n1; ++j)
+                    for (long i = 0; i < n0; ++i) {
+                        long ijk[3] = {i, j, k};
+                        size_t q = fidx(s, i, j, k);
+                        double sum = 0.0;
+                        int any = 0;
+                        for (int b = 0; b < 3; ++b) {
+                            if (b == a || !s->eoff[off_slot(a, b)]) continue;
+                            double o = s->eoff[off_slot(a, b)][q];
+                            if (o == 0.0) continue;
+                            sum += o * mean_nearest(s, U[b], a, b, ijk);
+                            any = 1;
+                        }
+                        if (any) s->E[a][q] += dt * sum;
+                    }
+        }
     for (int c = 0; c < 3; ++c) {
         Emid[c] = (double*)malloc(sizeof(double) * s->len);
         memcpy(Emid[c], s->E[c], sizeof(double) * s->len);
@@ -1228,7 +1287,7 @@ static void e_step(or_sim* s, double t_half)
                     s->E[c][b] = Eold[c][bi] + kc * (Emid[c][bi] - Eold[c][b]);
                 }
     }
-    for (int c = 0; c < 3; ++c) { free(Eold[c]); free(Emid[c]); }
+    for (int c = 0; c < 3; ++c) { free(Eold[c]); free(Emid[c]); free(U[c]); }
 }
 
 /* ------------------------------------------------------------------------- */
@@ -1430,6 +1489,39 @@ int or_set_eps_inv(or_sim* s, const double* einv)
         s->einv[c] = (double*)malloc(sizeof(double) * s->len);
         if (!s->einv[c]) return -2;
         memcpy(s->einv[c], einv + c * s->len, sizeof(double) * s->len);
+    }
+    return 0;
+}
+
+/* Off-diagonal entries may be nonzero only where, on every open axis, the
+ * node index lies in [2, n - 2]: the averaged update terms then come from
+ * interior nodes (never a Mur face or padding). */
+int or_set_eps_offdiag(or_sim* s, const double* e)
+{
+    if (e) {
+        for (int m = 0; m < 6; ++m) {
+            int a = m / 2;
+            int half[3];
+            stag_E(a, half);
+            for (int k = 0; k < s->L[2]; ++k)
+                for (int j = 0; j < s->L[1]; ++j)
+                    for (int i = 0; i < s->L[0]; ++i) {
+                        double v = e[(size_t)m * s->len + ((size_t)k * s->L[1] + j) * s->L[0] + i];
+                        if (!isfinite(v)) return -1;
+                        if (v == 0.0) continue;
+                        int ijk[3] = {i, j, k};
+                        for (int x = 0; x < 3; ++x)
+                            if (is_open(s, x) && (ijk[x] < 2 || ijk[x] > s->g.n[x] - 2)) return -1;
+                    }
+        }
+    }
+    for (int m = 0; m < 6; ++m) {
+        free(s->eoff[m]);
+        s->eoff[m] = NULL;
+        if (!e) continue;
+        s->eoff[m] = (double*)malloc(sizeof(double) * s->len);
+        if (!s->eoff[m]) return -2;
+        memcpy(s->eoff[m], e + (size_t)m * s->len, sizeof(double) * s->len);
     }
     return 0;
 }

@@ -138,6 +138,12 @@ int  or_get_fields(const or_sim* s, double* e, double* b);   /* [3][L] each */
  * einv[3][L] holds the inverse permittivity of component c at the E_c node
  * (NULL restores the unit tensor).  Entries must be finite and positive. */
 int  or_set_eps_inv(or_sim* s, const double* einv);
+/* The off-diagonal entries of the inverse dielectric tensor, e[6][L]: row a,
+ * column b != a at the E_a node, in the order 01 02 10 12 20 21 (NULL: none).
+ * The update term of component b is averaged onto the E_a node from its four
+ * (two, one) nearest E_b nodes.  Entries must be finite, and nonzero only at
+ * node indices in [2, n - 2] on every open axis. */
+int  or_set_eps_offdiag(or_sim* s, const double* e);
 /* Sec. 2 relaxation study: macroparticle kinetic-energy histogram of species
  * sid, nbins bins over [0, e_max) joules plus counts[nbins] at or above it. */
 int  or_energy_histogram(const or_sim* s, int sid, double e_max, int nbins, uint64_t* counts);

@@ -190,10 +190,12 @@ def stream(n_requests=512, rate_hz=None, seed=7, scale=1.0):
 
 
 def with_dielectric(w: dict, eps, region=None) -> dict:
-    """A copy of workload w with a constant background permittivity eps = [eps_x, eps_y, eps_z]
-    (diagonal) inside region (default: the region of the first species), vacuum elsewhere."""
+    """A copy of workload w with a constant background permittivity inside region (default: the
+    region of the first species), vacuum elsewhere.  eps is [eps_x, eps_y, eps_z] (a diagonal
+    tensor) or a 3x3 tensor (its inverse then has off-diagonal entries)."""
     w = copy.deepcopy(w)
-    w["dielectric"] = {"eps": [float(e) for e in eps],
+    e = np.asarray(eps, dtype=float)
+    w["dielectric"] = {"eps": e.tolist(),
                        "region": copy.deepcopy(region or w["species"][0]["region"])}
     w["name"] = w["name"] + "_eps"
     return w
@@ -271,33 +273,73 @@ def field_extent(w: dict):
     return [w["n"][a] + (1 if a < w["dims"] and not w["periodic"][a] else 0) for a in range(3)]
 
 
-def eps_inv_map(w: dict):
-    """Inverse permittivity per E component at its Yee node ([3][L2][L1][L0]): 1/eps_c where the node
-    (half-integer along c, integer along the other active axes, in cell units) lies in the dielectric
-    region, 1 elsewhere.  None when the workload has no dielectric."""
-    d = w.get("dielectric")
-    if d is None:
-        return None
+def _eps_inverse(d: dict):
+    """The inverse permittivity tensor of a dielectric description (diagonal or 3x3)."""
+    e = np.asarray(d["eps"], dtype=float)
+    return np.diag(1.0 / e) if e.ndim == 1 else np.linalg.inv(e)
+
+
+def _inside(w: dict, reg: dict, c: int):
+    """Mask of the E_c nodes ([L2][L1][L0]) inside region reg."""
     L = field_extent(w)
     dims = w["dims"]
     kk, jj, ii = np.meshgrid(np.arange(L[2], dtype=float), np.arange(L[1], dtype=float),
                              np.arange(L[0], dtype=float), indexing="ij")
-    out = np.ones((3, L[2], L[1], L[0]))
-    reg = d["region"]
+    pos = [ii, jj, kk]
+    if c < dims:
+        pos[c] = pos[c] + 0.5
+    if reg["kind"] == "ball":
+        r2 = sum((pos[a] - reg["center"][a]) ** 2 for a in range(dims))
+        return r2 <= reg["radius"] ** 2
+    if reg["kind"] == "box":
+        inside = np.ones_like(ii, dtype=bool)
+        for a in range(dims):
+            inside &= (pos[a] >= reg["lo"][a]) & (pos[a] < reg["hi"][a])
+        return inside
+    return np.ones_like(ii, dtype=bool)
+
+
+def eps_offdiag_map(w: dict):
+    """Off-diagonal inverse permittivity ([6][L2][L1][L0], row a, column b != a at the E_a node, in
+    the order 01 02 10 12 20 21) of a full-tensor dielectric inside its region.  Entries within two
+    nodes of an open face are left zero (the media end before the absorbing faces).  None when the
+    workload has no dielectric or a diagonal one."""
+    d = w.get("dielectric")
+    if d is None or np.asarray(d["eps"]).ndim == 1:
+        return None
+    inv = _eps_inverse(d)
+    L = field_extent(w)
+    keep = np.ones((L[2], L[1], L[0]), dtype=bool)
+    for a in range(w["dims"]):
+        if not w["periodic"][a]:
+            idx = np.arange(L[a])
+            ok = (idx >= 2) & (idx <= w["n"][a] - 2)
+            shape = [1, 1, 1]
+            shape[2 - a] = L[a]
+            keep &= ok.reshape(shape)
+    out = np.zeros((6, L[2], L[1], L[0]))
+    m = 0
+    for a in range(3):
+        mask = _inside(w, d["region"], a) & keep
+        for b in range(3):
+            if b == a:
+                continue
+            out[m][mask] = inv[a, b]
+            m += 1
+    return out
+
+
+def eps_inv_map(w: dict):
+    """Inverse permittivity per E component at its Yee node ([3][L2][L1][L0]): the diagonal entry
+    (eps^-1)_cc where the node (half-integer along c, integer along the other active axes, in cell
+    units) lies in the dielectric region, 1 elsewhere.  None when the workload has no dielectric."""
+    d = w.get("dielectric")
+    if d is None:
+        return None
+    inv = _eps_inverse(d)
+    out = np.ones([3] + field_extent(w)[::-1])
     for c in range(3):
-        pos = [ii.copy(), jj.copy(), kk.copy()]
-        if c < dims:
-            pos[c] += 0.5
-        if reg["kind"] == "ball":
-            r2 = sum((pos[a] - reg["center"][a]) ** 2 for a in range(dims))
-            inside = r2 <= reg["radius"] ** 2
-        elif reg["kind"] == "box":
-            inside = np.ones_like(ii, dtype=bool)
-            for a in range(dims):
-                inside &= (pos[a] >= reg["lo"][a]) & (pos[a] < reg["hi"][a])
-        else:
-            inside = np.ones_like(ii, dtype=bool)
-        out[c][inside] = 1.0 / d["eps"][c]
+        out[c][_inside(w, d["region"], c)] = inv[c, c]
     return out
 
 
