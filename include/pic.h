@@ -82,6 +82,8 @@ typedef struct {
     double src_tau;     /* [s]     */
     int eps_cells;      /* 1: a per-cell diagonal inverse permittivity (eq:consteps) scales  */
                         /* the E update; set by pic_load_eps_inv, unit until then.           */
+                        /* 2: as 1, plus off-diagonal entries (pic_load_eps_offdiag; zero    */
+                        /* until then); not with track_continuity, not in a batch.           */
                         /* 0: the unit tensor (no arena space, no extra reads)               */
     int ext_field;      /* 1: a static external field (pic_load_ext_field; zero until then)   */
                         /* is added to E where the particles gather it                        */
@@ -169,12 +171,29 @@ int pic_load_fields(pic_sim* s, const double* e, const double* b);
  * node, E_c += dt einv (c^2 (curl B)_c - J_c / eps0).  The field energy uses
  * eps0 E^2 / (2 einv) and the Gauss residual div(E / einv).  Open faces keep
  * the vacuum Mur update (their entries are not used), so media should end
- * before them.  Needs eps_cells = 1; until this call the tensor is the unit
- * one.  Entries must be finite and positive, and dt must stay below the
+ * before them.  Needs eps_cells = 1 or 2; until this call the tensor is the
+ * unit one.  Entries must be finite and positive, and dt must stay below the
  * stability limit with the fastest light speed c sqrt(max einv).
  * Synchronous.  Errors: PIC_EINVAL (eps_cells = 0, null or bad entries),
  * PIC_ECFL, PIC_ESTATE (not bound, or in a batch), PIC_EDEVICE. */
 int pic_load_eps_inv(pic_sim* s, const double* einv);
+
+/* Sec. 4, eq:consteps with a full (anisotropic, spatially varying) tensor:
+ * set its off-diagonal entries e[6][L] (FP64, L the extent of
+ * pic_field_shape): row a, column b != a at the E_a node, in the order
+ * (a, b) = 01 02 10 12 20 21.  The E_a update gains dt sum_b e_ab U_b, where
+ * U_b = c^2 (curl B)_b - J_b / eps0 is averaged onto the E_a node from the
+ * E_b nodes nearest to it: the four (two where only one of a, b is an active
+ * axis, one where neither is) at index offsets +s along a and -t along b,
+ * s, t in {0, 1}.  On the device the term is folded into the current that
+ * the field kernel reads.  Entries must be finite, and nonzero only at node
+ * indices in [2, n - 2] along every open axis.  dt must stay below the
+ * stability limit with c^2 scaled by the largest diagonal entry plus the
+ * largest row sum of |off-diagonal entries| (a Gershgorin bound).  The
+ * field energy and the Gauss residual keep using the diagonal.  Needs
+ * eps_cells = 2.  Synchronous.  Errors: PIC_EINVAL (eps_cells != 2, null or
+ * bad entries), PIC_ECFL, PIC_ESTATE (not bound, or in a batch), PIC_EDEVICE. */
+int pic_load_eps_offdiag(pic_sim* s, const double* e);
 
 /* Sec. 3: set the static external electrostatic field (the work-function
  * barrier) e[3][L] (FP64 V/m, L the extent of pic_field_shape), entry

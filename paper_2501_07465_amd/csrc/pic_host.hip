@@ -71,6 +71,7 @@ struct pic_sim {
     int batch_refs = 0;      // member of a batch
     SimDev* d_batch = nullptr;  // the member's entry in the batch table
     double einv_max = 1.0;   // largest loaded inverse permittivity (1 for the unit tensor)
+    double eoff_max = 0.0;   // largest row sum of |off-diagonal inverse permittivity|
 };
 
 // The device table the kernels of this simulation must read: its own, or its batch entry.
@@ -147,7 +148,9 @@ static int setup_grid(pic_sim* s)
         return fail(s, PIC_EINVAL, "block must be 64, 128, 256 or 512");
     if (g.series_cap <= 0) g.series_cap = 8192;
     if (g.unit < 0 || (g.unit > 0 && g.unit < 64)) return fail(s, PIC_EINVAL, "unit must be 0 or >= 64");
-    if (g.eps_cells != 0 && g.eps_cells != 1) return fail(s, PIC_EINVAL, "eps_cells must be 0 or 1");
+    if (g.eps_cells < 0 || g.eps_cells > 2) return fail(s, PIC_EINVAL, "eps_cells must be 0, 1 or 2");
+    if (g.eps_cells == 2 && g.track_continuity)
+        return fail(s, PIC_EINVAL, "a full dielectric tensor folds its off-diagonal term into the current: no continuity tracking");
     if (g.ext_field != 0 && g.ext_field != 1) return fail(s, PIC_EINVAL, "ext_field must be 0 or 1");
     memset(&h, 0, sizeof(h));
     h.unit_cap = g.unit;
@@ -409,7 +412,7 @@ extern "C" int pic_init_species(pic_sim* s, const pic_species_desc* d, uint64_t 
             for (auto& v : x.cdf) v /= tot;
         }
     }
-    if (int r = check_dt(s, &x, s->einv_max)) return r;
+    if (int r = check_dt(s, &x, s->einv_max + s->eoff_max)) return r;
     const int sid = (int)s->sp.size();
     s->sp.push_back(std::move(x));
     if (species_id) *species_id = sid;
@@ -521,6 +524,8 @@ static size_t plan(pic_sim* s, char* base, bool assign)
     h.rho_b = P.take<double>(L);
     h.jtrack = h.track ? P.takeb(3 * L * es) : nullptr;
     h.einv = s->g.eps_cells ? P.takeb(3 * L * es) : nullptr;
+    h.eoff = s->g.eps_cells == 2 ? P.takeb(6 * L * es) : nullptr;
+    h.tu = s->g.eps_cells == 2 ? P.takeb(3 * L * es) : nullptr;
     h.eext = s->g.ext_field ? P.takeb(3 * L * es) : nullptr;
     h.red = P.take<double>(16);
     h.hist = P.take<unsigned long long>(kMaxHistBins + 1);
@@ -670,6 +675,7 @@ extern "C" int pic_bind(pic_sim* s, void* dev_arena, size_t bytes, void* hip_str
         else HIPCHK(s, enqueue_fill_pattern(s->h.einv, nb, 0u, 0x3ff00000u, s->st));
     }
     s->einv_max = 1.0;
+    s->eoff_max = 0.0;
     int r = upload_table(s);
     if (r) return r;
     for (size_t i = 0; i < s->sp.size(); ++i) {
@@ -808,12 +814,51 @@ extern "C" int pic_load_eps_inv(pic_sim* s, const double* einv)
         if (s->es == 4 && !(einv[q] >= 1e-30 && einv[q] <= 1e30)) return fail(s, PIC_EINVAL, "einv entry %zu out of FP32 range", q);
         mx = std::max(mx, einv[q]);
     }
-    if (int r = check_dt(s, nullptr, mx)) return r;
+    if (int r = check_dt(s, nullptr, mx + s->eoff_max)) return r;
     std::vector<char> buf;
     if (s->es == 4) to_real<float>(einv, 3 * L, buf); else to_real<double>(einv, 3 * L, buf);
     HIPCHK(s, hipMemcpyAsync(s->h.einv, buf.data(), buf.size(), hipMemcpyHostToDevice, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     s->einv_max = mx;
+    return PIC_OK;
+}
+
+extern "C" int pic_load_eps_offdiag(pic_sim* s, const double* e)
+{
+    if (!s) return PIC_EINVAL;
+    if (!s->bound) return fail(s, PIC_ESTATE, "bind before loading the permittivity");
+    if (s->batch_refs) return fail(s, PIC_ESTATE, "simulation is in a batch");
+    if (!s->h.eoff) return fail(s, PIC_EINVAL, "the grid was created without eps_cells = 2");
+    if (!e) return fail(s, PIC_EINVAL, "null entries");
+    const size_t L = (size_t)s->h.Lvol;
+    const int L0 = s->h.L[0], L1 = s->h.L[1];
+    double rowmax = 0.0;
+    for (size_t q = 0; q < L; ++q) {
+        const int g[3] = {(int)(q % L0), (int)((q / L0) % L1), (int)(q / ((size_t)L0 * L1))};
+        // the averaged update terms must come from interior nodes: indices [2, n - 2] on open axes
+        bool edge = false;
+        for (int a = 0; a < s->g.dims; ++a)
+            if (!s->h.periodic[a] && (g[a] < 2 || g[a] > s->h.n[a] - 2)) edge = true;
+        for (int a = 0; a < 3; ++a) {
+            double row = 0.0;
+            for (int k = 0; k < 2; ++k) {
+                const size_t i = (size_t)(2 * a + k) * L + q;
+                const double v = e[i];
+                if (!std::isfinite(v) || (s->es == 4 && !(std::fabs(v) < 1e30)))
+                    return fail(s, PIC_EINVAL, "off-diagonal entry %zu is not finite", i);
+                if (v != 0.0 && edge)
+                    return fail(s, PIC_EINVAL, "off-diagonal entry %zu lies within two nodes of an open face", i);
+                row += std::fabs(v);
+            }
+            rowmax = std::max(rowmax, row);
+        }
+    }
+    if (int r = check_dt(s, nullptr, s->einv_max + rowmax)) return r;
+    std::vector<char> buf;
+    if (s->es == 4) to_real<float>(e, 6 * L, buf); else to_real<double>(e, 6 * L, buf);
+    HIPCHK(s, hipMemcpyAsync(s->h.eoff, buf.data(), buf.size(), hipMemcpyHostToDevice, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    s->eoff_max = rowmax;
     return PIC_OK;
 }
 
@@ -909,6 +954,7 @@ static Launch make_launch(pic_sim* s)
     L.eps = s->h.einv != nullptr;
     L.rare = has_rare(s);
     L.ext = s->h.eext != nullptr;
+    L.tensor_lvol = s->h.eoff ? s->h.Lvol : 0;
     L.stream = s->st;
     return L;
 }
@@ -1326,6 +1372,7 @@ extern "C" int pic_batch_add(pic_batch* b, pic_sim* s)
     if (!b->members.empty() && s->g.sort_every != b->members[0]->g.sort_every)
         return bfail(b, PIC_EINVAL, "members must share the sort period");
     if (s->h.track) return bfail(b, PIC_EINVAL, "continuity tracking is not batched");
+    if (s->h.eoff) return bfail(b, PIC_EINVAL, "a full dielectric tensor is not batched");
     if (s->step % s->g.sort_every != 0) return bfail(b, PIC_ESTATE, "member must be at a multiple of its sort period");
     if (s->st != b->st) return bfail(b, PIC_EINVAL, "member must be bound to the batch stream");
     // first sort (bound species) outside the batch graph

@@ -127,6 +127,9 @@ struct SimDev {
     int track;             // keep the merged particle current of the last step
     void* jtrack;          // [3][Lvol] R
     void* einv;            // [3][Lvol] R: inverse permittivity at the E_c nodes, or null (unit tensor)
+    void* eoff;            // [6][Lvol] R: off-diagonal inverse permittivity (a, b) at the E_a nodes,
+                           // order 01 02 10 12 20 21, or null (diagonal tensor)
+    void* tu;              // [3][Lvol] R: update terms c^2 curl B - J / eps0 of the full-tensor step
     void* eext;            // [3][Lvol] R: static external field at the E_c nodes felt by the particles, or null
     double* rho_ion;       // [Lvol]
     double* rho_a;         // [Lvol]
@@ -172,6 +175,7 @@ struct Launch {
     bool eps;              // some member has a per-cell inverse permittivity
     bool rare;             // some member has a species with diffusive walls or per-carrier Dirac mass
     bool ext;              // some member has a static external field
+    long long tensor_lvol; // field nodes of a simulation with a full tensor (0: none; never batched)
     hipStream_t stream;
 };
 

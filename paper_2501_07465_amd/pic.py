@@ -33,7 +33,7 @@ PIC_SRC_NONE, PIC_SRC_SHEET, PIC_SRC_POINT = 0, 1, 2
  DIAG_EXPORT_CURRENT, DIAG_KEYS) = range(12)
 
 EXPORTED = ["pic_create", "pic_init_species", "pic_footprint", "pic_bind", "pic_load_particles",
-            "pic_load_fields", "pic_load_eps_inv", "pic_load_ext_field", "pic_field_shape", "pic_init_fields", "pic_step", "pic_use_graphs",
+            "pic_load_fields", "pic_load_eps_inv", "pic_load_eps_offdiag", "pic_load_ext_field", "pic_field_shape", "pic_init_fields", "pic_step", "pic_use_graphs",
             "pic_diag", "pic_energy_histogram", "pic_time_kernels", "pic_sync", "pic_species_count", "pic_last_error", "pic_destroy",
             "pic_batch_footprint", "pic_batch_create", "pic_batch_add", "pic_batch_remove",
             "pic_batch_step", "pic_batch_size", "pic_batch_last_error", "pic_batch_destroy"]
@@ -85,6 +85,7 @@ def lib():
         L.pic_load_particles.argtypes = [_VP, C.c_int, _D, _D, _D, C.c_size_t]
         L.pic_load_fields.argtypes = [_VP, _D, _D]
         L.pic_load_eps_inv.argtypes = [_VP, _D]
+        L.pic_load_eps_offdiag.argtypes = [_VP, _D]
         L.pic_load_ext_field.argtypes = [_VP, _D]
         L.pic_energy_histogram.argtypes = [_VP, C.c_int, C.c_double, C.c_int, C.POINTER(C.c_uint64)]
         L.pic_field_shape.argtypes = [_VP, C.POINTER(C.c_int)]
@@ -169,6 +170,11 @@ def pic_load_fields(h, e=None, b=None):
 def pic_load_eps_inv(h, einv):
     einv = np.ascontiguousarray(einv, dtype=np.float64)
     _check(lib().pic_load_eps_inv(h, einv.ctypes.data_as(_D)), h)
+
+
+def pic_load_eps_offdiag(h, eoff):
+    eoff = np.ascontiguousarray(eoff, dtype=np.float64)
+    _check(lib().pic_load_eps_offdiag(h, eoff.ctypes.data_as(_D)), h)
 
 
 def pic_load_ext_field(h, e):
@@ -289,7 +295,8 @@ def grid_desc(w: dict, precision: str | None = None, track_continuity: bool = Fa
     g.sort_every = w.get("sort_every", 20)
     g.series_cap = series_cap or max(1, int(w.get("steps", 1000)) + 64)
     g.track_continuity = int(track_continuity)
-    g.eps_cells = int(w.get("dielectric") is not None)
+    d = w.get("dielectric")
+    g.eps_cells = 0 if d is None else (1 if np.asarray(d["eps"]).ndim == 1 else 2)
     g.ext_field = int(w.get("wall") is not None)
     src = w.get("source", {"kind": "none"})
     g.src_kind = _SRC[src["kind"]]
@@ -374,6 +381,9 @@ class Simulation:
         if w.get("dielectric") is not None:
             from . import workloads
             pic_load_eps_inv(self.h, workloads.eps_inv_map(w))
+            off = workloads.eps_offdiag_map(w)
+            if off is not None:
+                pic_load_eps_offdiag(self.h, off)
         if w.get("wall") is not None:
             from . import workloads
             pic_load_ext_field(self.h, workloads.wall_field(w))

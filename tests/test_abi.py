@@ -175,7 +175,34 @@ def test_dielectric_arena_and_validation():
         pic.pic_destroy(h0)
         pic.pic_destroy(h1)
     g = pic.grid_desc(W.small("disk2d"))
-    g.eps_cells = 2
+    g.eps_cells = 3
+    with pytest.raises(pic.PicError) as e:
+        pic.pic_create(g)
+    assert e.value.code == pic.PIC_EINVAL
+
+
+def test_full_tensor_arena_and_validation():
+    """eps_cells = 2 adds the diagonal, the six off-diagonal arrays and the three update-term arrays;
+    it is refused with continuity tracking; the off-diagonal load needs a bound simulation."""
+    from paper_2501_07465_amd import pic, workloads as W
+    eps = [[3.0, 0.4, 0.0], [0.4, 2.0, 0.0], [0.0, 0.0, 4.0]]
+    for prec, es in (("fp32", 4), ("fp64", 8)):
+        w = W.small("disk2d")
+        h0 = pic.pic_create(pic.grid_desc(w, prec))
+        we = W.with_dielectric(w, eps)
+        g = pic.grid_desc(we, prec)
+        assert g.eps_cells == 2
+        h1 = pic.pic_create(g)
+        L = pic.pic_field_shape(h1)
+        extra = pic.pic_footprint(h1) - pic.pic_footprint(h0)
+        need = 12 * L[0] * L[1] * L[2] * es
+        assert need <= extra < need + 3 * 256
+        with pytest.raises(pic.PicError) as e:
+            pic.pic_load_eps_offdiag(h1, W.eps_offdiag_map(we))
+        assert e.value.code == pic.PIC_ESTATE
+        pic.pic_destroy(h0)
+        pic.pic_destroy(h1)
+    g = pic.grid_desc(W.with_dielectric(W.small("disk2d"), eps), track_continuity=True)
     with pytest.raises(pic.PicError) as e:
         pic.pic_create(g)
     assert e.value.code == pic.PIC_EINVAL

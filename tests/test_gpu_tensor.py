@@ -1,0 +1,160 @@
+"""The full inverse dielectric tensor (Sec. 4, eq:consteps, anisotropic with off-diagonal entries) on
+the device, through the C ABI.
+
+The device folds the off-diagonal row, applied to the update terms averaged from the nearest nodes
+of the other components, into the current its field kernel reads; the oracle adds it to E
+directly.  FP64: element by element within 1e-12 of the oracle's scale from the same state on
+every dimensionality (the disk also with every in-plane face open), with the same diagonal-weighted
+field energy; the diagonal-only run ends elsewhere.  FP32: ten steps of the fields alone within
+1e-5.  Graph replays equal plain launches (up to the order of atomic additions).  Refusals:
+batching, a grid without eps_cells = 2, entries near an open face, a tensor beyond the Courant
+limit.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TENSOR = {"slab1d": ([[2.0, 0.0, 0.0], [0.0, 3.0, 0.6], [0.0, 0.6, 4.0]],
+                     {"kind": "box", "lo": [20.0, 0.0, 0.0], "hi": [44.0, 1.0, 1.0]}),
+          "disk2d": ([[3.7, 0.5, 0.3], [0.5, 3.0, 0.2], [0.3, 0.2, 2.5]], None),
+          "sheet2d": ([[2.1, 0.3, 0.0], [0.3, 2.4, 0.1], [0.0, 0.1, 2.2]], "substrate"),
+          "sphere3d": ([[2.0, 0.4, 0.2], [0.4, 3.0, 0.3], [0.2, 0.3, 4.0]], None)}
+
+
+def _tensor(name, fp64=True):
+    from paper_2501_07465_amd import workloads as W
+    w = W.small(name)
+    if name == "sphere3d" and fp64:
+        w["tile"] = [4, 4, 4]  # FP64 3D windows within 64 KiB of LDS
+    eps, reg = TENSOR[name]
+    if reg == "substrate":
+        reg = w["species"][1]["region"]
+    return W.with_dielectric(w, eps, reg)
+
+
+def _rel(a, b, scale=None):
+    scale = np.max(np.abs(b)) if scale is None else scale
+    return float(np.max(np.abs(a - b)) / max(scale, 1e-300)) if a.size else 0.0
+
+
+def _compare(sim, ref, w, tol, label):
+    for sid in range(len(w["species"])):
+        xg, vg, _ = sim.particles(sid)
+        xr, vr, _ = ref.particles(sid)
+        ex = float(np.max(np.abs(xg - xr) / np.array(w["dx"]))) if len(xg) else 0.0
+        ev = _rel(vg, vr)
+        print(f"{label} species {sid}: x err {ex:.2e} cells, v rel {ev:.2e}", flush=True)
+        assert ex < tol and ev < tol, (label, sid, ex, ev)
+    eg, bg = sim.fields()
+    er, br = ref.fields()
+    ee, eb = _rel(eg, er), _rel(bg, br, max(np.max(np.abs(br)), np.max(np.abs(er)) / 3e8))
+    print(f"{label} fields: E rel {ee:.2e}, B rel {eb:.2e}", flush=True)
+    assert ee < tol and eb < tol, (label, ee, eb)
+
+
+@pytest.mark.parametrize("name,steps", [("slab1d", 60), ("disk2d", 40), ("sheet2d", 40), ("sphere3d", 20)])
+def test_fp64_tensor_matches_oracle(oracle, name, steps):
+    from paper_2501_07465_amd import pic, workloads as W
+    w = _tensor(name)
+    print(f"case fp64 full tensor {name} {steps} steps", flush=True)
+    ref = oracle.build_workload(w)
+    st, fl = ref.state(), ref.fields()
+    sim = pic.Simulation(w, precision="fp64", states=st, fields=fl, graphs=False)
+    sim.step(steps)
+    ref.step(steps)
+    _compare(sim, ref, w, 1e-12, f"fp64 tensor {name}")
+    assert abs(sim.field_energy() / ref.field_energy() - 1.0) < 1e-12
+    # the off-diagonal entries change the run
+    diag = oracle.Sim(w)
+    for sid, (x, v, xi, wt) in enumerate(st):
+        diag.add_species(w["species"][sid], wt, x, v, xi)
+    diag.set_eps_inv(W.eps_inv_map(w))
+    diag.set_fields(*fl)
+    diag.step(steps)
+    d = _rel(diag.fields()[0], ref.fields()[0])
+    print(f"diagonal-only vs full tensor oracle runs: E rel {d:.2e}", flush=True)
+    assert d > 1e-6
+
+
+def test_fp64_tensor_open_faces_2d(oracle):
+    from paper_2501_07465_amd import pic
+    w = _tensor("disk2d")
+    w["periodic"] = [0, 0, 1]
+    w["source"]["index"] = [6, 0, 0]
+    print("case fp64 full tensor disk all open", flush=True)
+    ref = oracle.build_workload(w)
+    sim = pic.Simulation(w, precision="fp64", states=ref.state(), fields=ref.fields(), graphs=False)
+    sim.step(60)
+    ref.step(60)
+    _compare(sim, ref, w, 1e-12, "fp64 tensor disk open")
+
+
+@pytest.mark.parametrize("name", ["disk2d", "sheet2d", "sphere3d", "slab1d"])
+def test_fp32_tensor_fields(oracle, name):
+    from paper_2501_07465_amd import pic, workloads as W
+    w = _tensor(name, fp64=False)
+    print(f"case fp32 full tensor fields {name}", flush=True)
+    base = oracle.build_workload(w)
+    base.step(5)
+    e, b = base.fields()
+    e32, b32 = e.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)
+    wf = dict(w)
+    wf["species"] = []
+    ref = oracle.Sim(wf)
+    ref.set_eps_inv(W.eps_inv_map(wf))
+    ref.set_eps_offdiag(W.eps_offdiag_map(wf))
+    ref.set_fields(e32, b32)
+    sim = pic.Simulation(wf, precision="fp32", fields=(e32, b32), graphs=False)
+    sim.step(10)
+    ref.step(10)
+    eg, bg = sim.fields()
+    er, br = ref.fields()
+    ee, eb = _rel(eg, er), _rel(bg, br)
+    print(f"fp32 tensor {name}: E rel {ee:.2e}, B rel {eb:.2e}", flush=True)
+    assert ee <= 1e-5 and eb <= 1e-5, (name, ee, eb)
+
+
+def test_tensor_graphs_equal_plain_launches(oracle):
+    from paper_2501_07465_amd import pic
+    w = _tensor("disk2d")
+    print("case full tensor graphs", flush=True)
+    ref = oracle.build_workload(w)
+    plain = pic.Simulation(w, precision="fp64", states=ref.state(), fields=ref.fields(), graphs=False)
+    capt = pic.Simulation(w, precision="fp64", states=ref.state(), fields=ref.fields(), graphs=True)
+    plain.step(60)
+    capt.step(60)
+    # equal up to the order of the deposit's atomic additions
+    for sid in range(len(w["species"])):
+        dv = _rel(capt.particles(sid)[1], plain.particles(sid)[1])
+        print(f"graphs vs plain species {sid}: v rel {dv:.2e}", flush=True)
+        assert dv < 1e-12
+    de = _rel(capt.fields()[0], plain.fields()[0])
+    print(f"graphs vs plain fields: E rel {de:.2e}", flush=True)
+    assert de < 1e-12
+
+
+def test_tensor_refusals():
+    from paper_2501_07465_amd import pic, workloads as W
+    w = _tensor("disk2d")
+    print("case full tensor refusals", flush=True)
+    batch = pic.Batch(2, 2, "fp64")
+    sim = pic.Simulation(w, precision="fp64", graphs=False, stream=batch.stream)
+    with pytest.raises(pic.PicError) as e:
+        batch.add(sim)
+    assert e.value.code == pic.PIC_EINVAL
+    L = pic.pic_field_shape(sim.h)
+    off = np.zeros((6, L[2], L[1], L[0]))
+    off[0, 0, 10, 1] = 0.05            # x is open on the disk: index 1 is too close to the face
+    with pytest.raises(pic.PicError) as e:
+        pic.pic_load_eps_offdiag(sim.h, off)
+    assert e.value.code == pic.PIC_EINVAL
+    off[0, 0, 10, 1] = 0.0
+    off[0, 0, 10, 10] = 50.0           # a row sum far beyond the Courant limit
+    with pytest.raises(pic.PicError) as e:
+        pic.pic_load_eps_offdiag(sim.h, off)
+    assert e.value.code == pic.PIC_ECFL
+    diag = pic.Simulation(W.with_dielectric(W.small("disk2d"), [3.0, 3.0, 3.0]), precision="fp64", graphs=False)
+    with pytest.raises(pic.PicError) as e:
+        pic.pic_load_eps_offdiag(diag.h, np.zeros((6, L[2], L[1], L[0])))
+    assert e.value.code == pic.PIC_EINVAL
