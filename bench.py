@@ -12,7 +12,9 @@ on the host on a bounded sample (cpu_baseline).
 
 A dielectric leg runs the same workload with the metal's background permittivity (eps = 3.7 by
 default) inside the disk, as a per-cell inverse permittivity (eq:consteps), and reports its rate
-and its field kernel against the kernel without one.
+and its field kernel against the kernel without one.  A tensor leg does the same with a full
+(anisotropic, off-diagonal) permittivity tensor in the disk, whose field step adds two
+node-parallel passes (update terms, off-diagonal fold) before the field kernel.
 
 Algorithmic bytes (the minimum the method moves; no halos or re-reads):
   particle kernel, per launch: per particle its state read and written (FP32: 1D/2D/3D free
@@ -21,7 +23,10 @@ Algorithmic bytes (the minimum the method moves; no halos or re-reads):
   whole step: particle kernel bytes + per cell 48 B (E, B read and written by the Yee update) +
   per occupied cell 12 B (J read by the Yee update);
   dielectric field kernel, per launch: per cell 48 B of E, B + 12 B of inverse permittivity, per
-  occupied cell 12 B of J.
+  occupied cell 12 B of J;
+  full-tensor field step (three kernels): the dielectric kernel reading J at every cell (72 B per
+  cell), the update-term pass (E, B, J read, U written: 48 B per cell) and the fold (off-diagonal
+  entries read: 24 B per cell; per folded node U, inverse permittivity and J read, J written: 48 B).
 achieved = bytes / average duration measured here with HIP events on the simulation's stream;
 peak = 8 TB/s HBM3E.  ``traffic`` is the kernel's measured HBM bytes per launch from committed
 rocprofv3 FETCH_SIZE/WRITE_SIZE runs (calibrated against a copy of known size) when those runs
@@ -190,6 +195,8 @@ def main():
     ap.add_argument("--eps-inf", type=float, default=3.7,
                     help="background permittivity of the metal for the dielectric leg (0: skip it)")
     ap.add_argument("--eps-steps", type=int, default=400)
+    ap.add_argument("--no-tensor", action="store_true", help="skip the full-tensor dielectric leg")
+    ap.add_argument("--no-diagonal", action="store_true", help="skip the diagonal dielectric leg")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-scale", type=float, default=0.25)
     ap.add_argument("--serve-load", type=float, default=0.75)
@@ -201,6 +208,7 @@ def main():
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    import numpy as np
     import torch
     from paper_2501_07465_amd import autotune, workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -291,7 +299,7 @@ def main():
                           "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS},
         "field_energy_end": fe,
     }
-    if args.eps_inf > 0:
+    if args.eps_inf > 0 and not args.no_diagonal:
         # the same workload with a per-cell inverse permittivity (the metal's background eps inside the
         # first species' region): the dielectric variant of the field kernel reads 3 more values per node
         we = W.with_dielectric(w, [args.eps_inf] * 3)
@@ -308,6 +316,26 @@ def main():
             "field_roofline": {"bound": "hbm", "achieved": f_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": f_gbs / HBM_PEAK_GBS, "bytes_per_launch": f_bytes,
                                "kernel": f"k_fields<{w['dims']},float,true>"}}
+    if args.eps_inf > 0 and not args.no_tensor:
+        # a full tensor: the background permittivity with in-plane and out-of-plane off-diagonal terms
+        e = args.eps_inf
+        eps_t = [[e, 0.1 * e, 0.05 * e], [0.1 * e, 0.9 * e, 0.05 * e], [0.05 * e, 0.05 * e, 1.1 * e]]
+        wt = W.with_dielectric(w, eps_t)
+        nfold = int(np.count_nonzero(np.any(W.eps_offdiag_map(wt) != 0, axis=0)))
+        log(f"bench: full-tensor leg, {nfold} folded nodes")
+        _, dtt, ktt, _ = run_gpu(wt, "fp32", args.eps_steps, 20, graphs, args.time_kernels, block)
+        t_bytes = ncells * 18 * es + ncells * 12 * es + ncells * 6 * es + nfold * 12 * es
+        t_ms = float(ktt[1])
+        t_gbs = t_bytes / (t_ms * 1e-3) / 1e9
+        line["tensor"] = {
+            "eps": eps_t, "region": wt["dielectric"]["region"]["kind"], "steps": args.eps_steps,
+            "folded_nodes": nfold, "value": npart * args.eps_steps / dtt, "unit": "particle-steps/s",
+            "ms_per_step": dtt / args.eps_steps * 1e3,
+            "kernels_ms": {"particles": float(ktt[0]), "field_step": t_ms, "fields_without": float(kt[1])},
+            "field_roofline": {"bound": "hbm", "achieved": t_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": t_gbs / HBM_PEAK_GBS, "bytes_per_step": t_bytes,
+                               "kernels": [f"k_tensor_u<{w['dims']},float>", f"k_tensor_fold<{w['dims']},float>",
+                                           f"k_fields<{w['dims']},float,true>"]}}
     if args.serve_requests > 0:
         line["serve"] = run_serve(args.serve_requests, args.serve_scale, args.serve_load, block,
                                   None, args.serve_budget_gib, args.serve_slots, log, w.get("unit", 0))

@@ -526,6 +526,8 @@ static size_t plan(pic_sim* s, char* base, bool assign)
     h.einv = s->g.eps_cells ? P.takeb(3 * L * es) : nullptr;
     h.eoff = s->g.eps_cells == 2 ? P.takeb(6 * L * es) : nullptr;
     h.tu = s->g.eps_cells == 2 ? P.takeb(3 * L * es) : nullptr;
+    h.tlist = s->g.eps_cells == 2 ? P.take<int>(2 * L) : nullptr;
+    h.tcount = s->g.eps_cells == 2 ? P.take<int>(2) : nullptr;
     h.eext = s->g.ext_field ? P.takeb(3 * L * es) : nullptr;
     h.red = P.take<double>(16);
     h.hist = P.take<unsigned long long>(kMaxHistBins + 1);
@@ -854,9 +856,36 @@ extern "C" int pic_load_eps_offdiag(pic_sim* s, const double* e)
         }
     }
     if (int r = check_dt(s, nullptr, s->einv_max + rowmax)) return r;
+    // the nodes with an off-diagonal row, and the nodes their averages read (+s e_a - t e_b)
+    std::vector<char> need(L, 0);
+    std::vector<int> lists(2 * L), counts(2, 0);
+    for (size_t q = 0; q < L; ++q) {
+        const int g[3] = {(int)(q % L0), (int)((q / L0) % L1), (int)(q / ((size_t)L0 * L1))};
+        bool row = false;
+        for (int m = 0; m < 6; ++m) {
+            if (e[(size_t)m * L + q] == 0.0) continue;
+            row = true;
+            const int a = m / 2, b = (m % 2) < a ? (m % 2) : (m % 2) + 1;
+            const int ns = a < s->g.dims ? 2 : 1, nt = b < s->g.dims ? 2 : 1;
+            for (int sa = 0; sa < ns; ++sa)
+                for (int tb = 0; tb < nt; ++tb) {
+                    int h[3] = {g[0], g[1], g[2]};
+                    h[a] += sa;
+                    h[b] -= tb;
+                    for (int x = 0; x < s->g.dims; ++x)
+                        if (s->h.periodic[x]) h[x] = (h[x] % s->h.n[x] + s->h.n[x]) % s->h.n[x];
+                    need[((size_t)h[2] * L1 + h[1]) * L0 + h[0]] = 1;
+                }
+        }
+        if (row) lists[L + counts[1]++] = (int)q;
+    }
+    for (size_t q = 0; q < L; ++q)
+        if (need[q]) lists[counts[0]++] = (int)q;
     std::vector<char> buf;
     if (s->es == 4) to_real<float>(e, 6 * L, buf); else to_real<double>(e, 6 * L, buf);
     HIPCHK(s, hipMemcpyAsync(s->h.eoff, buf.data(), buf.size(), hipMemcpyHostToDevice, s->st));
+    HIPCHK(s, hipMemcpyAsync(s->h.tlist, lists.data(), lists.size() * sizeof(int), hipMemcpyHostToDevice, s->st));
+    HIPCHK(s, hipMemcpyAsync(s->h.tcount, counts.data(), 2 * sizeof(int), hipMemcpyHostToDevice, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     s->eoff_max = rowmax;
     return PIC_OK;

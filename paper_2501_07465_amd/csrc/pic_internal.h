@@ -130,6 +130,9 @@ struct SimDev {
     void* eoff;            // [6][Lvol] R: off-diagonal inverse permittivity (a, b) at the E_a nodes,
                            // order 01 02 10 12 20 21, or null (diagonal tensor)
     void* tu;              // [3][Lvol] R: update terms c^2 curl B - J / eps0 of the full-tensor step
+    int* tlist;            // [2][Lvol]: nodes whose update terms are averaged, then nodes with an
+                           // off-diagonal row (ascending; built when the entries are loaded)
+    int* tcount;           // [2]: lengths of the two lists
     void* eext;            // [3][Lvol] R: static external field at the E_c nodes felt by the particles, or null
     double* rho_ion;       // [Lvol]
     double* rho_a;         // [Lvol]

@@ -182,7 +182,8 @@ def test_dielectric_arena_and_validation():
 
 
 def test_full_tensor_arena_and_validation():
-    """eps_cells = 2 adds the diagonal, the six off-diagonal arrays and the three update-term arrays;
+    """eps_cells = 2 adds the diagonal, the six off-diagonal arrays, the three update-term arrays and
+    two node lists;
     it is refused with continuity tracking; the off-diagonal load needs a bound simulation."""
     from paper_2501_07465_amd import pic, workloads as W
     eps = [[3.0, 0.4, 0.0], [0.4, 2.0, 0.0], [0.0, 0.0, 4.0]]
@@ -195,8 +196,9 @@ def test_full_tensor_arena_and_validation():
         h1 = pic.pic_create(g)
         L = pic.pic_field_shape(h1)
         extra = pic.pic_footprint(h1) - pic.pic_footprint(h0)
-        need = 12 * L[0] * L[1] * L[2] * es
-        assert need <= extra < need + 3 * 256
+        nodes = L[0] * L[1] * L[2]
+        need = 12 * nodes * es + 2 * nodes * 4 + 2 * 4   # + the two node lists and their lengths
+        assert need <= extra < need + 5 * 256
         with pytest.raises(pic.PicError) as e:
             pic.pic_load_eps_offdiag(h1, W.eps_offdiag_map(we))
         assert e.value.code == pic.PIC_ESTATE
