@@ -158,3 +158,35 @@ def test_tensor_refusals():
     with pytest.raises(pic.PicError) as e:
         pic.pic_load_eps_offdiag(diag.h, np.zeros((6, L[2], L[1], L[0])))
     assert e.value.code == pic.PIC_EINVAL
+
+
+def test_fullsize_tensor_fields(oracle):
+    """The full disk (1024 x 1024 cells) with the tensor of the benchmark's tensor leg, fields alone
+    from seeded random FP32 fields (the source kept): ten FP32 steps within 1e-5 of the oracle."""
+    from paper_2501_07465_amd import pic, workloads as W
+    w = W.WORKLOADS["disk2d"]()
+    e = 3.7
+    eps_t = [[e, 0.1 * e, 0.05 * e], [0.1 * e, 0.9 * e, 0.05 * e], [0.05 * e, 0.05 * e, 1.1 * e]]
+    wt = W.with_dielectric(w, eps_t)
+    wt["species"] = []
+    print("case full-size tensor fields 1024x1024", flush=True)
+    L = W.field_extent(wt)
+    rng = np.random.default_rng(23)
+    shp = (3, L[2], L[1], L[0])
+    e0 = rng.normal(size=shp).astype(np.float32).astype(np.float64) * 1e8
+    b0 = rng.normal(size=shp).astype(np.float32).astype(np.float64) * 0.3
+    e0[0, :, :, -1] = 0.0   # padding of the open x axis (E_x, B_y, B_z are half-located along x)
+    b0[1, :, :, -1] = 0.0
+    b0[2, :, :, -1] = 0.0
+    ref = oracle.Sim(wt)
+    ref.set_eps_inv(W.eps_inv_map(wt))
+    ref.set_eps_offdiag(W.eps_offdiag_map(wt))
+    ref.set_fields(e0, b0)
+    sim = pic.Simulation(wt, precision="fp32", fields=(e0, b0), graphs=True)
+    sim.step(10)
+    ref.step(10)
+    eg, bg = sim.fields()
+    er, br = ref.fields()
+    ee, eb = _rel(eg, er), _rel(bg, br)
+    print(f"full-size fp32 tensor fields: E rel {ee:.2e}, B rel {eb:.2e}", flush=True)
+    assert ee <= 1e-5 and eb <= 1e-5
