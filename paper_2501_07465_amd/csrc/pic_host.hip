@@ -222,6 +222,9 @@ static int setup_grid(pic_sim* s)
         h.nftiles *= h.nft[a];
         h.Lvol *= h.L[a];
     }
+    // the full tensor's node lists hold int32 node indices
+    if (g.eps_cells == 2 && h.Lvol > 0x7fffffffLL)
+        return fail(s, PIC_EINVAL, "a full dielectric tensor needs fewer than 2^31 field nodes");
     int fl = 1;
     {
         int ve = 1, vb = 1, vj = 1;
