@@ -14,7 +14,9 @@ A dielectric leg runs the same workload with the metal's background permittivity
 default) inside the disk, as a per-cell inverse permittivity (eq:consteps), and reports its rate
 and its field kernel against the kernel without one.  A tensor leg does the same with a full
 (anisotropic, off-diagonal) permittivity tensor in the disk, whose field step adds two
-node-parallel passes (update terms, off-diagonal fold) before the field kernel.
+node-parallel passes (update terms, off-diagonal fold) before the field kernel.  Variant legs time
+the other optional physics at full size against the plain workload: diffusive walls and the
+work-function barrier on the disk, the per-carrier Dirac mass and diffusive ribbon ends on the sheet.
 
 Algorithmic bytes (the minimum the method moves; no halos or re-reads):
   particle kernel, per launch: per particle its state read and written (FP32: 1D/2D/3D free
@@ -117,6 +119,41 @@ def run_gpu(w, precision, steps, warmup, graphs=True, time_kernels=0, block=256)
     return counts, dt, kt, fe
 
 
+def run_variants(w, block, kt, npart, value, args, graphs, log):
+    """The optional physics at full size, FP32, each against its plain workload: particle-steps/s,
+    ms per step and the particle kernel's event time."""
+    from paper_2501_07465_amd import autotune, workloads as W
+    steps, tk = args.variant_steps, 100
+
+    def leg(wv, label, blk):
+        log(f"bench: variant {label}")
+        counts, dtv, ktv, _ = run_gpu(wv, "fp32", steps, 20, graphs, tk, blk)
+        n = sum(counts)
+        return {"value": n * steps / dtv, "unit": "particle-steps/s", "ms_per_step": dtv / steps * 1e3,
+                "particle_kernel_ms": float(ktv[0]), "particles": n}
+
+    out = {"steps": steps,
+           "disk_plain": {"value": value, "particle_kernel_ms": float(kt[0]), "particles": npart},
+           "f3a_diffuse_walls": leg(W.with_diffuse_walls(w), "diffuse walls (disk)", block),
+           "f3b_work_function": leg(W.with_potential_wall(w, 9.8, 2.0), "work-function barrier (disk)", block)}
+    ws = W.WORKLOADS["sheet2d"]()
+    res = autotune.shipped(ws, "fp32")
+    bs = 256
+    if res is not None:
+        ws = autotune.apply(ws, res)
+        bs = int(res["block"])
+    out["sheet_plain"] = leg(ws, "plain (sheet)", bs)
+    wm = copy.deepcopy(ws)
+    wm["species"][0]["mass_per_particle"] = True
+    out["g11_dirac_mass"] = leg(wm, "per-carrier Dirac mass (sheet)", bs)
+    wr = copy.deepcopy(ws)
+    reg = wr["species"][0]["region"]
+    reg["lo"][0], reg["hi"][0] = 64.0, float(wr["n"][0] - 64)
+    wr["species"][0].update(reflect=True, scatter="diffuse")
+    out["f3c_ribbon_edges"] = leg(wr, "diffusive ribbon ends (sheet)", bs)
+    return out
+
+
 def committed_traffic(workload, tile, block, unit):
     """Traffic per launch from the committed counter summary, if it matches the current kernels."""
     from paper_2501_07465_amd import profiling
@@ -197,6 +234,9 @@ def main():
     ap.add_argument("--eps-steps", type=int, default=400)
     ap.add_argument("--no-tensor", action="store_true", help="skip the full-tensor dielectric leg")
     ap.add_argument("--no-diagonal", action="store_true", help="skip the diagonal dielectric leg")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the legs of the other optional physics (walls, barrier, Dirac mass, ribbon)")
+    ap.add_argument("--variant-steps", type=int, default=400)
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-scale", type=float, default=0.25)
     ap.add_argument("--serve-load", type=float, default=0.75)
@@ -336,6 +376,8 @@ def main():
                                "frac": t_gbs / HBM_PEAK_GBS, "bytes_per_step": t_bytes,
                                "kernels": [f"k_tensor_u<{w['dims']},float>", f"k_tensor_fold<{w['dims']},float>",
                                            f"k_fields<{w['dims']},float,true>"]}}
+    if not args.no_variants and args.workload == "disk2d":
+        line["variants"] = run_variants(w, block, kt, npart, line["value"], args, graphs, log)
     if args.serve_requests > 0:
         line["serve"] = run_serve(args.serve_requests, args.serve_scale, args.serve_load, block,
                                   None, args.serve_budget_gib, args.serve_slots, log, w.get("unit", 0))

@@ -965,11 +965,21 @@ static int enqueue_sort_all(pic_sim* s, std::vector<int>* sorted)
     return PIC_OK;
 }
 
-// species options whose code lives only in the RARE particle kernels
+// species options whose code lives only in the RARE particle kernels (the diffusive redraw)
 static bool has_rare(const pic_sim* s)
 {
     for (const auto& x : s->sp)
-        if (x.d.reflect == 2 || (x.d.kind == PIC_DIRAC && x.d.mass_per_particle)) return true;
+        if (x.d.reflect == 2) return true;
+    return false;
+}
+
+// options whose extra loads live only in the EXT particle kernels: the static external field and
+// the per-carrier Dirac mass
+static bool has_extra(const pic_sim* s)
+{
+    if (s->h.eext) return true;
+    for (const auto& x : s->sp)
+        if (x.d.kind == PIC_DIRAC && x.d.mass_per_particle) return true;
     return false;
 }
 
@@ -985,7 +995,7 @@ static Launch make_launch(pic_sim* s)
     L.ftiles_total = s->h.nftiles;
     L.eps = s->h.einv != nullptr;
     L.rare = has_rare(s);
-    L.ext = s->h.eext != nullptr;
+    L.ext = has_extra(s);
     L.tensor_lvol = s->h.eoff ? s->h.Lvol : 0;
     L.stream = s->st;
     return L;
@@ -1471,7 +1481,7 @@ static int batch_enqueue_period(pic_batch* b, std::vector<std::vector<int>>* sor
         block = std::max(block, s->g.block);
         eps = eps || s->h.einv != nullptr;
         rare = rare || has_rare(s);
-        ext = ext || s->h.eext != nullptr;
+        ext = ext || has_extra(s);
     }
     Launch L{};
     L.sims = b->table;

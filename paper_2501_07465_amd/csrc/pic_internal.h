@@ -176,8 +176,8 @@ struct Launch {
     int block;             // particle-kernel block
     int ftiles_total;      // field tiles over members
     bool eps;              // some member has a per-cell inverse permittivity
-    bool rare;             // some member has a species with diffusive walls or per-carrier Dirac mass
-    bool ext;              // some member has a static external field
+    bool rare;             // some member has a species with diffusive walls
+    bool ext;              // some member has a static external field or per-carrier Dirac mass
     long long tensor_lvol; // field nodes of a simulation with a full tensor (0: none; never batched)
     hipStream_t stream;
 };
