@@ -83,7 +83,7 @@ typedef struct {
     int eps_cells;      /* 1: a per-cell diagonal inverse permittivity (eq:consteps) scales  */
                         /* the E update; set by pic_load_eps_inv, unit until then.           */
                         /* 2: as 1, plus off-diagonal entries (pic_load_eps_offdiag; zero    */
-                        /* until then); not with track_continuity, not in a batch.           */
+                        /* until then); not with track_continuity.                           */
                         /* 0: the unit tensor (no arena space, no extra reads)               */
     int ext_field;      /* 1: a static external field (pic_load_ext_field; zero until then)   */
                         /* is added to E where the particles gather it                        */

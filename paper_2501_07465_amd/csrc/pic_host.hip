@@ -1414,7 +1414,6 @@ extern "C" int pic_batch_add(pic_batch* b, pic_sim* s)
     if (!b->members.empty() && s->g.sort_every != b->members[0]->g.sort_every)
         return bfail(b, PIC_EINVAL, "members must share the sort period");
     if (s->h.track) return bfail(b, PIC_EINVAL, "continuity tracking is not batched");
-    if (s->h.eoff) return bfail(b, PIC_EINVAL, "a full dielectric tensor is not batched");
     if (s->step % s->g.sort_every != 0) return bfail(b, PIC_ESTATE, "member must be at a multiple of its sort period");
     if (s->st != b->st) return bfail(b, PIC_EINVAL, "member must be bound to the batch stream");
     // first sort (bound species) outside the batch graph
@@ -1498,13 +1497,16 @@ static int batch_enqueue_period(pic_batch* b, std::vector<std::vector<int>>* sor
     const int P = b->members[0]->g.sort_every;
     for (int k = 0; k < P; ++k) {
         hipError_t e;
-        if (b->precision == PIC_FP32) {
-            e = Launchers<float>::particles(b->dims, L);
-            if (e == hipSuccess) e = Launchers<float>::fields(b->dims, L, lds);
-        } else {
-            e = Launchers<double>::particles(b->dims, L);
-            if (e == hipSuccess) e = Launchers<double>::fields(b->dims, L, lds);
+        const bool f32 = b->precision == PIC_FP32;
+        e = f32 ? Launchers<float>::particles(b->dims, L) : Launchers<double>::particles(b->dims, L);
+        // members with a full tensor fold its off-diagonal part into their current first
+        for (int i = 0; i < n && e == hipSuccess; ++i) {
+            const pic_sim* s = b->members[i];
+            if (!s->h.eoff) continue;
+            e = f32 ? Launchers<float>::tensor(b->dims, b->table + i, s->h.Lvol, b->st)
+                    : Launchers<double>::tensor(b->dims, b->table + i, s->h.Lvol, b->st);
         }
+        if (e == hipSuccess) e = f32 ? Launchers<float>::fields(b->dims, L, lds) : Launchers<double>::fields(b->dims, L, lds);
         if (e != hipSuccess) return bfail(b, PIC_EDEVICE, hipGetErrorString(e));
     }
     return PIC_OK;

@@ -178,7 +178,8 @@ struct Launch {
     bool eps;              // some member has a per-cell inverse permittivity
     bool rare;             // some member has a species with diffusive walls
     bool ext;              // some member has a static external field or per-carrier Dirac mass
-    long long tensor_lvol; // field nodes of a simulation with a full tensor (0: none; never batched)
+    long long tensor_lvol; // field nodes of a simulation with a full tensor (0: none; a batch launches
+                           // each tensor member's passes itself, through Launchers::tensor)
     hipStream_t stream;
 };
 
@@ -198,6 +199,8 @@ template <typename R>
 struct Launchers {
     static hipError_t particles(int dims, const Launch& L);
     static hipError_t fields(int dims, const Launch& L, int lds_elems);
+    // the full-tensor passes of one simulation (its device table entry, its field nodes)
+    static hipError_t tensor(int dims, const SimDev* entry, long long lvol, hipStream_t st);
     static hipError_t load(int dims, SimDev* dS, const LoadArgs& A, hipStream_t st);
     static hipError_t field_energy(const SimDev* dS, int par, double* part, int nb, hipStream_t st);
     static hipError_t kinetic(const SimDev* dS, int s, double* part, int nb, hipStream_t st);

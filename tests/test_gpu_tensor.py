@@ -6,9 +6,9 @@ of the other components, into the current its field kernel reads; the oracle add
 directly.  FP64: element by element within 1e-12 of the oracle's scale from the same state on
 every dimensionality (the disk also with every in-plane face open), with the same diagonal-weighted
 field energy; the diagonal-only run ends elsewhere.  FP32: ten steps of the fields alone within
-1e-5.  Graph replays equal plain launches (up to the order of atomic additions).  Refusals:
-batching, a grid without eps_cells = 2, entries near an open face, a tensor beyond the Courant
-limit.
+1e-5, also at full size.  Graph replays equal plain launches (up to the order of atomic
+additions).  A batch with a tensor member and a plain one matches both oracle runs.  Refusals: a
+grid without eps_cells = 2, entries near an open face, a tensor beyond the Courant limit.
 """
 import numpy as np
 import pytest
@@ -134,15 +134,36 @@ def test_tensor_graphs_equal_plain_launches(oracle):
     assert de < 1e-12
 
 
+def test_batch_with_a_tensor_member_matches_oracle(oracle):
+    """A batch of a full-tensor member and a member without a dielectric: each member's tensor
+    passes run before the batch's field launch; both within 1e-12 of their own oracle runs."""
+    from paper_2501_07465_amd import pic, workloads as W
+    wa = _tensor("disk2d")
+    wb = W.small("disk2d")
+    print("case batch full tensor + plain", flush=True)
+    refa = oracle.build_workload(wa)
+    refb = oracle.build_workload(wb)
+    batch = pic.Batch(2, 2, "fp64")
+    sa = pic.Simulation(wa, precision="fp64", states=refa.state(), fields=refa.fields(), graphs=False,
+                        stream=batch.stream)
+    sb = pic.Simulation(wb, precision="fp64", states=refb.state(), fields=refb.fields(), graphs=False,
+                        stream=batch.stream)
+    batch.add(sa)
+    batch.add(sb)
+    batch.step(40)
+    refa.step(40)
+    refb.step(40)
+    batch.remove(sa)
+    batch.remove(sb)
+    _compare(sa, refa, wa, 1e-12, "batch tensor")
+    _compare(sb, refb, wb, 1e-12, "batch plain")
+
+
 def test_tensor_refusals():
     from paper_2501_07465_amd import pic, workloads as W
     w = _tensor("disk2d")
     print("case full tensor refusals", flush=True)
-    batch = pic.Batch(2, 2, "fp64")
-    sim = pic.Simulation(w, precision="fp64", graphs=False, stream=batch.stream)
-    with pytest.raises(pic.PicError) as e:
-        batch.add(sim)
-    assert e.value.code == pic.PIC_EINVAL
+    sim = pic.Simulation(w, precision="fp64", graphs=False)
     L = pic.pic_field_shape(sim.h)
     off = np.zeros((6, L[2], L[1], L[0]))
     off[0, 0, 10, 1] = 0.05            # x is open on the disk: index 1 is too close to the face
