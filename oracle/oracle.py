@@ -2,8 +2,10 @@
 
 TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()`` and
 the ``cpu_baseline`` leg of ``bench.py``.  The product path (the HIP library and
-its binding) never imports this module, and this module imports nothing from
-the product package.
+its binding) never imports this module.  From the product package this module
+imports only ``workloads``, the seeded input generator shared by both sides,
+which holds none of the method's arithmetic (it draws the inverse-permittivity
+and wall-field inputs that both sides load).
 
 Workloads arrive as plain dicts (see ``paper_2501_07465_amd.workloads``); every
 derived quantity that belongs to the method (density from E_F, Dirac mass,
