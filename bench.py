@@ -1,16 +1,21 @@
 """Benchmark of the PIC step on one MI355X: particle-steps/s (sort + gather + push + deposit + fields).
 
-Default workload: the 2D3V disk (1024 x 1024 cells of 1 nm, 200 nm metal disk, 16 ppc Fermi-Dirac
-free electrons + 16 ppc bound Lorentz electrons, 800 nm pulse at 1e9 V/m), FP32 form (int32 cell +
-FP32 offset), synthetic seeded inputs.  W warm-up steps, then exactly K timed steps (captured
-graphs replay one 20-step sort period at a time), bracketed by device synchronisation.
+Default workload (the headline): the 3D3V nanosphere, 256^3 cells of 1 nm with a metal sphere of
+radius 100 cells holding 8 ppc Fermi-Dirac free electrons + 8 ppc bound Lorentz electrons
+(65.5M particles), dipole pulse, cell sort every 20 steps, FP32 form (int32 cell + FP32 offset),
+synthetic seeded inputs.  The warm-up is rounded up to a whole number of 20-step sort periods, so
+the K timed steps start on a period boundary and replay captured graphs (one per period; a
+remainder of K runs as plain launches, reported in ``config``), bracketed by device
+synchronisation.
 
 Beside it: the FP64 GPU rate of the same workload and the FP32/FP64 speedup; a roofline for the
-dominant kernel (the particle kernel) and for the whole step; a serving run (continuous batching
-of seeded uneven requests with Poisson arrivals, p50/p99 latency); the plain-C FP64 oracle timed
-on the host on a bounded sample (cpu_baseline).
+dominant kernel (the particle kernel) and for the whole step; a secondary leg on the 2D3V disk
+(1024^2 cells, 16 + 16 ppc) with its own roofline; a serving run (continuous batching of seeded
+uneven requests with Poisson arrivals, p50/p99 latency); the plain-C FP64 oracle timed on the
+host's cores (cpu_baseline: concurrent single-threaded copies, each on a 64^3 twin of the sphere
+with the same ppc and physics).
 
-A dielectric leg runs the same workload with the metal's background permittivity (eps = 3.7 by
+A dielectric leg runs the disk with the metal's background permittivity (eps = 3.7 by
 default) inside the disk, as a per-cell inverse permittivity (eq:consteps), and reports its rate
 and its field kernel against the kernel without one.  A tensor leg does the same with a full
 (anisotropic, off-diagonal) permittivity tensor in the disk, whose field step adds two
@@ -27,8 +32,9 @@ Algorithmic bytes (the minimum the method moves; no halos or re-reads):
   dielectric field kernel, per launch: per cell 48 B of E, B + 12 B of inverse permittivity, per
   occupied cell 12 B of J;
   full-tensor field step (three kernels): the dielectric kernel reading J at every cell (72 B per
-  cell), the update-term pass (E, B, J read, U written: 48 B per cell) and the fold (off-diagonal
-  entries read: 24 B per cell; per folded node U, inverse permittivity and J read, J written: 48 B).
+  cell); the update-term pass over its node list (E, B gathered, J read, U written: 48 B per listed
+  node); the fold over the nodes with an off-diagonal row (entries, inverse permittivity and the
+  averaged U read, J read and written: 72 B per folded node).
 achieved = bytes / average duration measured here with HIP events on the simulation's stream;
 peak = 8 TB/s HBM3E.  ``traffic`` is the kernel's measured HBM bytes per launch from committed
 rocprofv3 FETCH_SIZE/WRITE_SIZE runs (calibrated against a copy of known size) when those runs
@@ -167,9 +173,21 @@ def committed_traffic(workload, tile, block, unit):
     return float(t["traffic_bytes"])
 
 
-def cpu_baseline(w, budget_s):
-    """The FP64 oracle on the host, on the first steps of the same workload."""
+def sphere_twin(seed):
+    """The 64^3 twin of the nanosphere: radius 25 cells, the same 8 + 8 ppc, species and cell size."""
+    from paper_2501_07465_amd import workloads as W
+    w = W.sphere3d(n=64, radius=25.0, src_gap=3)
+    w["name"] = "sphere3d_twin64"
+    w["seed"] = seed
+    return w
+
+
+def _oracle_worker(args):
+    """One single-threaded oracle process: load the twin, then step it for budget_s seconds."""
+    seed, budget_s = args
+    sys.path.insert(0, ROOT)
     from oracle import oracle as O
+    w = sphere_twin(seed)
     ref = O.build_workload(w)
     n = sum(ref.count(s) for s in range(len(w["species"])))
     t0 = time.perf_counter()
@@ -178,11 +196,38 @@ def cpu_baseline(w, budget_s):
         ref.step(1)
         steps += 1
         el = time.perf_counter() - t0
-        if el > budget_s or steps >= 200:
+        if el > budget_s:
             break
-    return {"value": n * steps / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{w['name']} full size ({n} particles), first {steps} steps after loading, "
-                      f"{el:.1f} s single-threaded plain C FP64"}
+    return n, steps, el
+
+
+def cpu_baseline(budget_s, log):
+    """The FP64 oracle on the host's cores: one single-threaded copy per core, each on its own seeded
+    64^3 twin of the sphere, all stepping concurrently for budget_s seconds (the oracle itself is
+    single-threaded, as written); aggregate particle-steps/s over the copies."""
+    import multiprocessing as mp
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    cores = max(1, min(16, ncpu))
+    from oracle import oracle as O
+    O.build()
+    log(f"bench: cpu baseline, {cores} oracle processes on the 64^3 sphere twin")
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(3 + 1000 * k, budget_s) for k in range(cores)])
+    wall = time.perf_counter() - t0
+    total = sum(n * st for n, st, _ in res)
+    rates = [n * st / el for n, st, el in res]
+    n0 = res[0][0]
+    return {"value": float(sum(rates)), "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+            "per_core": float(sum(rates) / cores),
+            "sample": f"{cores} concurrent single-threaded plain C FP64 oracle processes, each on a seeded "
+                      f"64^3 twin of the 256^3 sphere (radius 25 cells, 8 + 8 ppc, {n0} particles), "
+                      f"{budget_s:.0f} s of steps each after loading; {total} particle-steps in total, "
+                      f"{wall:.0f} s wall with loading"}
 
 
 def run_serve(n_req, scale, load, block, tile, budget_gib, slots, log, unit=None):
@@ -214,15 +259,83 @@ def run_serve(n_req, scale, load, block, tile, budget_gib, slots, log, unit=None
                              "free + 8-32 ppc bound, 500-4000 steps, FP32"}
 
 
+def tuned(name, log, autotune_now=False):
+    """Workload dict with its shipped (or freshly measured) tile, block and unit."""
+    from paper_2501_07465_amd import autotune, workloads as W
+    w = W.WORKLOADS[name]()
+    res = None if autotune_now else autotune.shipped(w, "fp32")
+    how = "shipped"
+    if res is None:
+        log(f"bench: autotuning tile and block for {name}")
+        res = autotune.tune(w, "fp32", periods=2, use_cache=False, log=log)
+        how = "measured"
+    return autotune.apply(w, res), int(res["block"]), how
+
+
+def fp32_leg(w, block, steps, warmup, graphs, time_kernels, label, log):
+    """FP32 rate of workload w, its particle-kernel roofline and its whole-step byte rate."""
+    log(f"bench: {label} fp32 tile {w['tile'][:w['dims']]} block {block} warmup {warmup} steps {steps}")
+    counts, dt, kt, fe = run_gpu(w, "fp32", steps, warmup, graphs, time_kernels, block)
+    npart = sum(counts)
+    occ = occupied_cells(w)
+    ncells = 1
+    for a in range(w["dims"]):
+        ncells *= w["n"][a]
+    es = 4
+    bytes_particle = particle_bytes_per_step(w, counts, es) + occ * (6 * es + 3 * es)
+    bytes_step = bytes_particle + ncells * 12 * es + occ * 3 * es
+    t_particle_ms = float(kt[0])
+    achieved = bytes_particle / (t_particle_ms * 1e-3) / 1e9
+    ms_step = dt / steps * 1e3
+    step_gbs = bytes_step / (ms_step * 1e-3) / 1e9
+    return {
+        "rate": npart * steps / dt, "dt": dt, "npart": npart, "counts": counts, "occ": occ, "ncells": ncells,
+        "ms_step": ms_step, "kt": kt, "field_energy_end": fe,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": committed_traffic(w["name"], w["tile"][:w["dims"]], block, w.get("unit", 0)),
+                     "kernel": f"k_particles<{w['dims']},float,false,false>", "bytes_per_launch": bytes_particle},
+        "step_roofline": {"bytes_per_step": bytes_step, "achieved": step_gbs, "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS},
+        "kernels_ms": {"particles": t_particle_ms, "fields": float(kt[1]), "sort_per_sort": float(kt[2]),
+                       "particle_kernel_rate": npart / (t_particle_ms * 1e-3)},
+    }
+
+
+def tensor_list_sizes(wt):
+    """Lengths of the two node lists of the full-tensor passes: nodes whose update terms are averaged
+    (each folded node's neighbours +s e_a - t e_b over its nonzero entries) and folded nodes."""
+    import numpy as np
+    from paper_2501_07465_amd import workloads as W
+    off = W.eps_offdiag_map(wt)  # [6][z][y][x]
+    dims = wt["dims"]
+    fold = np.any(off != 0, axis=0)
+    need = np.zeros_like(fold)
+    for m in range(6):
+        a = m // 2
+        b = (m % 2) if (m % 2) < a else (m % 2) + 1
+        nz = off[m] != 0
+        for sa in range(2 if a < dims else 1):
+            for tb in range(2 if b < dims else 1):
+                shift = [0, 0, 0]
+                shift[a] += sa
+                shift[b] -= tb
+                # arrays are [z, y, x]; the entries lie away from open faces, so a roll is exact
+                need |= np.roll(nz, (shift[2], shift[1], shift[0]), axis=(0, 1, 2))
+    return int(need.sum()), int(fold.sum())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="disk2d")
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--workload", default="sphere3d")
+    ap.add_argument("--secondary", default="disk2d", help="second FP32 leg with its own roofline ('' skips it)")
+    ap.add_argument("--secondary-steps", type=int, default=4000)
     ap.add_argument("--no-graphs", action="store_true")
-    ap.add_argument("--fp64-steps", type=int, default=1000)
-    ap.add_argument("--time-kernels", type=int, default=200)
+    ap.add_argument("--fp64-steps", type=int, default=200)
+    ap.add_argument("--time-kernels", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", type=str, default=None, help="particle tile, e.g. 16x16 (default: tuned)")
@@ -230,7 +343,7 @@ def main():
     ap.add_argument("--unit", type=int, default=None, help="particles per work unit (default: tuned; 0 = tile)")
     ap.add_argument("--autotune", action="store_true", help="measure the tile/block/unit candidates now")
     ap.add_argument("--eps-inf", type=float, default=3.7,
-                    help="background permittivity of the metal for the dielectric leg (0: skip it)")
+                    help="background permittivity of the metal for the dielectric legs on the disk (0: skip)")
     ap.add_argument("--eps-steps", type=int, default=400)
     ap.add_argument("--no-tensor", action="store_true", help="skip the full-tensor dielectric leg")
     ap.add_argument("--no-diagonal", action="store_true", help="skip the diagonal dielectric leg")
@@ -256,10 +369,8 @@ def main():
     def log(m):
         print(m, file=sys.stderr, flush=True)
 
-    w = W.WORKLOADS[args.workload]()
-    tuning = "default"
-    block = 256
     if args.tile or args.block or args.unit is not None:
+        w = W.WORKLOADS[args.workload]()
         if args.tile:
             t = [int(v) for v in args.tile.split("x")]
             w["tile"] = t + [1] * (3 - len(t))
@@ -267,16 +378,12 @@ def main():
         w["unit"] = args.unit or 0
         tuning = "explicit"
     else:
-        res = None if args.autotune else autotune.shipped(w, "fp32")
-        tuning = "shipped"
-        if res is None:
-            log("bench: autotuning tile and block")
-            res = autotune.tune(w, "fp32", periods=2, use_cache=False, log=log)
-            tuning = "measured"
-        w = autotune.apply(w, res)
-        block = int(res["block"])
+        w, block, tuning = tuned(args.workload, log, args.autotune)
     tile = w["tile"][:w["dims"]]
     graphs = not args.no_graphs
+    P = int(w.get("sort_every", 20))
+    # the timed steps start on a sort-period boundary, so whole periods replay captured graphs
+    warmup = max(P, -(-args.warmup // P) * P)
     if args.calib_mib:
         a = torch.ones(args.calib_mib << 18, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -284,10 +391,8 @@ def main():
             torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
         del a, b
-    log(f"bench: {args.workload} fp32 tile {tile} block {block} warmup {args.warmup} steps {args.steps}")
-    counts, dt32, kt, fe = run_gpu(w, "fp32", args.steps, args.warmup, graphs, args.time_kernels, block)
-    npart = sum(counts)
-    rate32 = npart * args.steps / dt32
+    head = fp32_leg(w, block, args.steps, warmup, graphs, args.time_kernels, args.workload, log)
+    npart, rate32 = head["npart"], head["rate"]
     log(f"bench: fp32 {rate32:.3e} particle-steps/s; fp64 {args.fp64_steps} steps")
     fp64 = None
     if args.fp64_steps > 0:
@@ -297,21 +402,12 @@ def main():
         while autotune.lds_bytes(t64[:w["dims"]], w["dims"], "fp64", block) > autotune.LDS_BYTES:
             a = max(range(w["dims"]), key=lambda k: t64[k])
             t64[a] //= 2
-        _, dt64, _, _ = run_gpu(w64, "fp64", args.fp64_steps, 20, graphs, 0, block)
-        rate64 = npart * args.fp64_steps / dt64
-        fp64 = {"value": rate64, "unit": "particle-steps/s", "steps": args.fp64_steps, "tile": t64[:w["dims"]],
-                "ms_per_step": dt64 / args.fp64_steps * 1e3, "fp32_speedup": rate32 / rate64}
-    occ = occupied_cells(w)
-    ncells = 1
-    for a in range(w["dims"]):
-        ncells *= w["n"][a]
-    es = 4
-    bytes_particle = particle_bytes_per_step(w, counts, es) + occ * (6 * es + 3 * es)
-    bytes_step = bytes_particle + ncells * 12 * es + occ * 3 * es
-    t_particle_ms = float(kt[0])
-    achieved = bytes_particle / (t_particle_ms * 1e-3) / 1e9
-    ms_step = dt32 / args.steps * 1e3
-    step_gbs = bytes_step / (ms_step * 1e-3) / 1e9
+        fp64_steps = max(P, args.fp64_steps // P * P)
+        _, dt64, _, _ = run_gpu(w64, "fp64", fp64_steps, warmup, graphs, 0, block)
+        rate64 = npart * fp64_steps / dt64
+        fp64 = {"value": rate64, "unit": "particle-steps/s", "steps": fp64_steps, "warmup": warmup,
+                "tile": t64[:w["dims"]], "ms_per_step": dt64 / fp64_steps * 1e3, "fp32_speedup": rate32 / rate64,
+                "graph_replays": fp64_steps // P if graphs else 0}
     line = {
         "metric": METRIC,
         "value": rate32,
@@ -319,71 +415,81 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": describe(w, npart), "particles": npart, "cells": ncells, "occupied_cells": occ,
-                   "graphs": graphs, "tile": tile, "block": block, "unit": w.get("unit", 0), "tuning": tuning,
-                   "sort_every": 20},
+        "config": {"workload": describe(w, npart), "particles": npart, "cells": head["ncells"],
+                   "occupied_cells": head["occ"], "graphs": graphs, "tile": tile, "block": block,
+                   "unit": w.get("unit", 0), "tuning": tuning, "sort_every": P, "warmup_run": warmup,
+                   "graph_replays": args.steps // P if graphs else 0,
+                   "plain_steps": args.steps % P if graphs else args.steps},
         "fp64": fp64,
-        "kernels_ms": {"particles": t_particle_ms, "fields": float(kt[1]), "sort_per_sort": float(kt[2]),
-                       "particle_kernel_rate": npart / (t_particle_ms * 1e-3)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": committed_traffic(args.workload, tile, block, w.get("unit", 0)),
-                     "kernel": f"k_particles<{w['dims']},float,false,false>", "bytes_per_launch": bytes_particle},
-        "step_roofline": {"bytes_per_step": bytes_step, "achieved": step_gbs, "peak": HBM_PEAK_GBS,
-                          "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS},
-        "field_energy_end": fe,
+        "kernels_ms": head["kernels_ms"],
+        "roofline": head["roofline"],
+        "step_roofline": head["step_roofline"],
+        "field_energy_end": head["field_energy_end"],
     }
-    if args.eps_inf > 0 and not args.no_diagonal:
-        # the same workload with a per-cell inverse permittivity (the metal's background eps inside the
-        # first species' region): the dielectric variant of the field kernel reads 3 more values per node
-        we = W.with_dielectric(w, [args.eps_inf] * 3)
+    wd, bd = None, 256
+    if args.secondary:
+        wd, bd, _ = tuned(args.secondary, log)
+        sec = fp32_leg(wd, bd, args.secondary_steps, 200, graphs, args.time_kernels, args.secondary, log)
+        line["secondary"] = {"workload": describe(wd, sec["npart"]), "value": sec["rate"],
+                             "unit": "particle-steps/s", "steps": args.secondary_steps, "ms_per_step": sec["ms_step"],
+                             "tile": wd["tile"][:wd["dims"]], "block": bd, "unit_particles": wd.get("unit", 0),
+                             "kernels_ms": sec["kernels_ms"], "roofline": sec["roofline"],
+                             "step_roofline": sec["step_roofline"]}
+    if wd is not None and wd["name"] == "disk2d" and args.eps_inf > 0 and not args.no_diagonal:
+        # the disk with a per-cell inverse permittivity (the metal's background eps inside the disk):
+        # the dielectric variant of the field kernel reads 3 more values per node
+        es = 4
+        ncd, occd = sec["ncells"], sec["occ"]
+        we = W.with_dielectric(wd, [args.eps_inf] * 3)
         log(f"bench: dielectric leg, eps {args.eps_inf} in {we['dielectric']['region']['kind']}")
-        _, dte, kte, _ = run_gpu(we, "fp32", args.eps_steps, 20, graphs, args.time_kernels, block)
-        f_bytes = ncells * 12 * es + occ * 3 * es + ncells * 3 * es
+        _, dte, kte, _ = run_gpu(we, "fp32", args.eps_steps, 20, graphs, args.time_kernels, bd)
+        f_bytes = ncd * 12 * es + occd * 3 * es + ncd * 3 * es
         f_ms = float(kte[1])
         f_gbs = f_bytes / (f_ms * 1e-3) / 1e9
         line["dielectric"] = {
-            "eps": [args.eps_inf] * 3, "region": we["dielectric"]["region"]["kind"], "steps": args.eps_steps,
-            "value": npart * args.eps_steps / dte, "unit": "particle-steps/s",
+            "workload": "disk2d", "eps": [args.eps_inf] * 3, "region": we["dielectric"]["region"]["kind"],
+            "steps": args.eps_steps, "value": sec["npart"] * args.eps_steps / dte, "unit": "particle-steps/s",
             "ms_per_step": dte / args.eps_steps * 1e3,
-            "kernels_ms": {"particles": float(kte[0]), "fields": f_ms, "fields_without": float(kt[1])},
+            "kernels_ms": {"particles": float(kte[0]), "fields": f_ms, "fields_without": float(sec["kt"][1])},
             "field_roofline": {"bound": "hbm", "achieved": f_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": f_gbs / HBM_PEAK_GBS, "bytes_per_launch": f_bytes,
-                               "kernel": f"k_fields<{w['dims']},float,true>"}}
-    if args.eps_inf > 0 and not args.no_tensor:
+                               "kernel": "k_fields<2,float,true>"}}
+    if wd is not None and wd["name"] == "disk2d" and args.eps_inf > 0 and not args.no_tensor:
         # a full tensor: the background permittivity with in-plane and out-of-plane off-diagonal terms
+        es = 4
         e = args.eps_inf
         eps_t = [[e, 0.1 * e, 0.05 * e], [0.1 * e, 0.9 * e, 0.05 * e], [0.05 * e, 0.05 * e, 1.1 * e]]
-        wt = W.with_dielectric(w, eps_t)
-        nfold = int(np.count_nonzero(np.any(W.eps_offdiag_map(wt) != 0, axis=0)))
-        log(f"bench: full-tensor leg, {nfold} folded nodes")
-        _, dtt, ktt, _ = run_gpu(wt, "fp32", args.eps_steps, 20, graphs, args.time_kernels, block)
-        t_bytes = ncells * 18 * es + ncells * 12 * es + ncells * 6 * es + nfold * 12 * es
+        wt = W.with_dielectric(wd, eps_t)
+        nu, nfold = tensor_list_sizes(wt)
+        log(f"bench: full-tensor leg, {nfold} folded nodes, {nu} update-term nodes")
+        _, dtt, ktt, _ = run_gpu(wt, "fp32", args.eps_steps, 20, graphs, args.time_kernels, bd)
+        t_bytes = sec["ncells"] * 18 * es + nu * 12 * es + nfold * 18 * es
         t_ms = float(ktt[1])
         t_gbs = t_bytes / (t_ms * 1e-3) / 1e9
         line["tensor"] = {
-            "eps": eps_t, "region": wt["dielectric"]["region"]["kind"], "steps": args.eps_steps,
-            "folded_nodes": nfold, "value": npart * args.eps_steps / dtt, "unit": "particle-steps/s",
+            "workload": "disk2d", "eps": eps_t, "region": wt["dielectric"]["region"]["kind"],
+            "steps": args.eps_steps, "folded_nodes": nfold, "update_term_nodes": nu,
+            "value": sec["npart"] * args.eps_steps / dtt, "unit": "particle-steps/s",
             "ms_per_step": dtt / args.eps_steps * 1e3,
-            "kernels_ms": {"particles": float(ktt[0]), "field_step": t_ms, "fields_without": float(kt[1])},
+            "kernels_ms": {"particles": float(ktt[0]), "field_step": t_ms, "fields_without": float(sec["kt"][1])},
             "field_roofline": {"bound": "hbm", "achieved": t_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": t_gbs / HBM_PEAK_GBS, "bytes_per_step": t_bytes,
-                               "kernels": [f"k_tensor_u<{w['dims']},float>", f"k_tensor_fold<{w['dims']},float>",
-                                           f"k_fields<{w['dims']},float,true>"]}}
-    if not args.no_variants and args.workload == "disk2d":
-        line["variants"] = run_variants(w, block, kt, npart, line["value"], args, graphs, log)
+                               "kernels": ["k_tensor_u<2,float>", "k_tensor_fold<2,float>",
+                                           "k_fields<2,float,true>"]}}
+    if wd is not None and wd["name"] == "disk2d" and not args.no_variants:
+        line["variants"] = run_variants(wd, bd, sec["kt"], sec["npart"], sec["rate"], args, graphs, log)
     if args.serve_requests > 0:
-        line["serve"] = run_serve(args.serve_requests, args.serve_scale, args.serve_load, block,
-                                  None, args.serve_budget_gib, args.serve_slots, log, w.get("unit", 0))
+        line["serve"] = run_serve(args.serve_requests, args.serve_scale, args.serve_load, bd,
+                                  None, args.serve_budget_gib, args.serve_slots, log,
+                                  wd.get("unit", 0) if wd is not None else 0)
     if not args.no_cpu:
-        log("bench: cpu baseline")
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, log)
     print(json.dumps(line))
 
 

@@ -162,7 +162,9 @@ int pic_load_particles(pic_sim* s, int sid, const double* x, const double* v,
                        const double* xi, size_t n);
 
 /* Copy fields in: e[3][L] and b[3][L] FP64 (B at integer time), where L is the
- * array extent of pic_field_shape().  Either may be NULL.  Synchronous. */
+ * array extent of pic_field_shape().  Either may be NULL.  Synchronous.
+ * Errors: PIC_EINVAL (a non-finite value; nothing is copied), PIC_ESTATE,
+ * PIC_EDEVICE. */
 int pic_load_fields(pic_sim* s, const double* e, const double* b);
 
 /* Sec. 4, eq:consteps: set the spatially varying dielectric tensor, diagonal,
@@ -215,17 +217,30 @@ int pic_field_shape(const pic_sim* s, int L[3]);
  * only).  Enqueued.  Errors: PIC_EINVAL, PIC_ESTATE. */
 int pic_init_fields(pic_sim* s, int mode);
 
-/* Enqueue nsteps steps of the PIC cycle.  Every sort_every steps (and after a
- * load) the particles of each species are cell-sorted by a stable integer
- * radix sort.  Returns enqueue errors only; device-side errors surface at the
- * next pic_diag/pic_sync.  Errors: PIC_ESTATE, PIC_EDEVICE. */
+/* Enqueue nsteps steps of the PIC cycle of Appendix A.1 with the field solver
+ * of Sec. 4.1: per step, gather E_n, B_n at x_n; push free particles by
+ * eq:borisscheme (rotation eq:borisrotsol), bound ones by eq:modborisscheme2
+ * (eq:modborisrotsol, or the gyrotropic rotation of eq:modborisBrot when
+ * b_weight != 0) and Dirac carriers by the renormalised push of Sec. 5, to
+ * v_{n+1/2} and x_{n+1} (eq:discrvel); reflect at the region boundary (Sec. 3);
+ * deposit J^{n+1/2} charge-conservingly; advance B half a step, E a step
+ * (eq:consteps) and B half a step, first-order Mur on open faces.  Every
+ * sort_every steps (and after a load) the particles of each species are
+ * cell-sorted by a stable integer radix sort.  A particle whose pushed velocity
+ * is not finite is held at rest and raises the flag of PIC_DIAG_NONFINITE_FLAG.
+ * Returns enqueue errors only; device-side errors surface at the next
+ * pic_diag/pic_sync.  Errors: PIC_ESTATE, PIC_EDEVICE. */
 int pic_step(pic_sim* s, int nsteps);
 
 /* Capture the steps in HIP graphs (one graph per sort period) and replay them
  * in pic_step.  on = 0 returns to plain launches. */
 int pic_use_graphs(pic_sim* s, int on);
 
-/* Diagnostics (FP64, computed on the device).  Synchronises the stream.
+/* Diagnostics of the state (FP64, computed on the device).  Synchronises the
+ * stream.  The energies are those of the fields (with the dielectric of
+ * eq:consteps weighting the electric part) and of the macroparticles
+ * (m w |v|^2 / 2, the carrier energy of eq:fddist); the Gauss residual checks
+ * the law the field solver of Sec. 4.1 keeps from its initial state.
  *   PIC_DIAG_FIELD_ENERGY       1 value  [J (per m^(3-dims))]
  *   PIC_DIAG_KINETIC_ENERGY     1 value per species (arg = species id, -1 all)
  *   PIC_DIAG_GAUSS_RESIDUAL     2 values: max|div E - rho/eps0|, max|rho_e|/eps0
@@ -239,6 +254,8 @@ int pic_use_graphs(pic_sim* s, int on);
  *   PIC_DIAG_EXPORT_FIELDS      e[3][L], b[3][L]
  *   PIC_DIAG_EXPORT_CURRENT     the last step's particle current J[3][L] (needs track_continuity)
  *   PIC_DIAG_KEYS               species arg: the cell key of each particle (as doubles)
+ *   PIC_DIAG_NONFINITE_FLAG     1 value: 1 if some step since pic_bind pushed a particle to a
+ *                               non-finite velocity (that particle was held at rest), else 0
  * Errors: PIC_ETRUNC (with *n_out set), PIC_EINVAL, PIC_ESTATE, PIC_EDEVICE,
  * PIC_ENONFINITE (a non-finite field energy or kinetic energy). */
 enum {
@@ -253,7 +270,8 @@ enum {
     PIC_DIAG_EXPORT_PARTICLES = 8,
     PIC_DIAG_EXPORT_FIELDS = 9,
     PIC_DIAG_EXPORT_CURRENT = 10,
-    PIC_DIAG_KEYS = 11
+    PIC_DIAG_KEYS = 11,
+    PIC_DIAG_NONFINITE_FLAG = 12
 };
 int pic_diag(pic_sim* s, int kind, int arg, double* out, size_t cap, size_t* n_out);
 

@@ -520,6 +520,7 @@ static size_t plan(pic_sim* s, char* base, bool assign)
     h.step_f = P.take<long long>(1);
     h.over_stamp = P.take<long long>(2);
     h.over_count = P.take<unsigned long long>(1);
+    h.nonfinite = P.take<int>(1);
     h.partials = P.take<double>((size_t)h.max_units * 3);
     h.series = P.take<double>((size_t)h.series_cap * 3);
     h.rho_ion = P.take<double>(L);
@@ -790,6 +791,10 @@ extern "C" int pic_load_fields(pic_sim* s, const double* e, const double* b)
     if (!s) return PIC_EINVAL;
     if (!s->bound) return fail(s, PIC_ESTATE, "bind before loading fields");
     const size_t L = (size_t)s->h.Lvol;
+    for (const double* src : {e, b})
+        if (src)
+            for (size_t q = 0; q < 3 * L; ++q)
+                if (!std::isfinite(src[q])) return fail(s, PIC_EINVAL, "non-finite field value at entry %zu", q);
     std::vector<char> buf;
     for (int c = 0; c < 3; ++c) {
         for (int w = 0; w < 2; ++w) {
@@ -1227,7 +1232,9 @@ extern "C" int pic_diag(pic_sim* s, int kind, int arg, double* out, size_t cap, 
     const int par = (int)(s->step & 1);  // field buffer holding the current E, B
     size_t need = 0;
     switch (kind) {
-    case PIC_DIAG_FIELD_ENERGY: case PIC_DIAG_STEP: case PIC_DIAG_OVERFLOW: need = 1; break;
+    case PIC_DIAG_FIELD_ENERGY: case PIC_DIAG_STEP: case PIC_DIAG_OVERFLOW: case PIC_DIAG_NONFINITE_FLAG:
+        need = 1;
+        break;
     case PIC_DIAG_KINETIC_ENERGY: need = arg < 0 ? nsp : 1; break;
     case PIC_DIAG_GAUSS_RESIDUAL: case PIC_DIAG_CONTINUITY: need = 2; break;
     case PIC_DIAG_CURRENT_SERIES: need = 3 * (size_t)std::min<long long>(s->step, s->h.series_cap); break;
@@ -1285,6 +1292,13 @@ extern "C" int pic_diag(pic_sim* s, int kind, int arg, double* out, size_t cap, 
         HIPCHK(s, hipMemcpyAsync(&c, s->h.over_count, sizeof(c), hipMemcpyDeviceToHost, s->st));
         HIPCHK(s, hipStreamSynchronize(s->st));
         out[0] = (double)c;
+        return PIC_OK;
+    }
+    case PIC_DIAG_NONFINITE_FLAG: {
+        int f = 0;
+        HIPCHK(s, hipMemcpyAsync(&f, s->h.nonfinite, sizeof(f), hipMemcpyDeviceToHost, s->st));
+        HIPCHK(s, hipStreamSynchronize(s->st));
+        out[0] = (double)f;
         return PIC_OK;
     }
     case PIC_DIAG_EXPORT_PARTICLES: {

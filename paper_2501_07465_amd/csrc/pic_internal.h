@@ -115,6 +115,7 @@ struct SimDev {
     int* fdirty;           // [2][nftiles] field tiles whose owned nodes of J[p] hold deposits
     long long* over_stamp; // [2] step+1 of the last overflow per parity
     unsigned long long* over_count;
+    int* nonfinite;        // set to 1 by the particle kernel when a pushed velocity is not finite
     double* partials;      // [max_units][3] per unit: sum q w v_{n+1/2}
     double* series;        // [series_cap][3]
     int series_cap;

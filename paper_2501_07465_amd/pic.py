@@ -30,7 +30,7 @@ PIC_LOAD_RANDOM, PIC_LOAD_QUIET = 0, 1
 PIC_SRC_NONE, PIC_SRC_SHEET, PIC_SRC_POINT = 0, 1, 2
 (DIAG_FIELD_ENERGY, DIAG_KINETIC_ENERGY, DIAG_GAUSS_RESIDUAL, DIAG_CONTINUITY, DIAG_CURRENT_SERIES,
  DIAG_PARTICLE_COUNT, DIAG_STEP, DIAG_OVERFLOW, DIAG_EXPORT_PARTICLES, DIAG_EXPORT_FIELDS,
- DIAG_EXPORT_CURRENT, DIAG_KEYS) = range(12)
+ DIAG_EXPORT_CURRENT, DIAG_KEYS, DIAG_NONFINITE_FLAG) = range(13)
 
 EXPORTED = ["pic_create", "pic_init_species", "pic_footprint", "pic_bind", "pic_load_particles",
             "pic_load_fields", "pic_load_eps_inv", "pic_load_eps_offdiag", "pic_load_ext_field", "pic_field_shape", "pic_init_fields", "pic_step", "pic_use_graphs",
@@ -450,6 +450,9 @@ class Simulation:
 
     def overflow(self):
         return int(pic_diag(self.h, DIAG_OVERFLOW)[0])
+
+    def nonfinite(self):
+        return int(pic_diag(self.h, DIAG_NONFINITE_FLAG)[0])
 
     @property
     def steps_done(self):

@@ -1,0 +1,93 @@
+"""FP64 diagnostics of the device against the oracle on the same state, and the non-finite flag.
+
+* Kinetic energy per species (m w |v|^2 / 2 summed in FP64 on the device) and the field energy
+  (with the dielectric weighting) within 1e-12 of the oracle's, FP64 form, after whole runs; the
+  FP32 form's diagnostics of the same FP32 state within 1e-6 (they are FP64 sums of FP32 values).
+* A velocity that overflows FP32 (finite in the FP64 input) is held at rest and raises
+  PIC_DIAG_NONFINITE_FLAG; the other particles run on, every value stays finite.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _small(name, fp64=True):
+    from paper_2501_07465_amd import workloads as W
+    w = W.small(name)
+    if name == "sphere3d" and fp64:
+        w["tile"] = [4, 4, 4]
+    return w
+
+
+@pytest.mark.parametrize("name,steps", [("slab1d", 60), ("disk2d", 40), ("sheet2d", 40), ("sphere3d", 20)])
+def test_fp64_energies_match_oracle(oracle, name, steps):
+    from paper_2501_07465_amd import pic
+    w = _small(name)
+    print(f"case energies fp64 {name}", flush=True)
+    ref = oracle.build_workload(w)
+    sim = pic.Simulation(w, precision="fp64", states=ref.state(), fields=ref.fields(), graphs=False)
+    for k in range(2):
+        sim.step(steps // 2)
+        ref.step(steps // 2)
+        for sid in range(len(w["species"])):
+            kg, kr = sim.kinetic_energy(sid), ref.kinetic_energy(sid)
+            print(f"{name} species {sid}: kinetic {kg:.6e} vs {kr:.6e}", flush=True)
+            assert kr > 0.0
+            assert abs(kg - kr) <= 1e-12 * abs(kr), (name, sid, kg, kr)
+        fg, fr = sim.field_energy(), ref.field_energy()
+        assert fr > 0.0
+        assert abs(fg - fr) <= 1e-12 * fr, (name, fg, fr)
+    allk = pic.pic_diag(sim.h, pic.DIAG_KINETIC_ENERGY, -1)
+    assert np.allclose(allk, [ref.kinetic_energy(s) for s in range(len(w["species"]))], rtol=1e-12, atol=0)
+    assert sim.nonfinite() == 0
+
+
+@pytest.mark.parametrize("name", ["disk2d", "sphere3d"])
+def test_fp32_energies_of_fp32_state(oracle, name):
+    """The FP32 form's FP64 diagnostics of its own state equal the oracle's diagnostics of that
+    state (loaded with the oracle loader's weights, which both loaders share)."""
+    from paper_2501_07465_amd import pic
+    w = _small(name, fp64=False)
+    print(f"case energies fp32 {name}", flush=True)
+    loaded = oracle.build_workload(w)
+    sim = pic.Simulation(w, precision="fp32", graphs=False)
+    sim.step(20)
+    ref = oracle.Sim(w)
+    for sid, sp in enumerate(w["species"]):
+        x, v, xi = sim.particles(sid)
+        ref.add_species(sp, loaded.weight(sid), x, v, xi if sp["kind"] == "bound" else None)
+    ref.set_fields(*sim.fields())
+    for sid in range(len(w["species"])):
+        kg, kr = sim.kinetic_energy(sid), ref.kinetic_energy(sid)
+        assert abs(kg - kr) <= 1e-6 * abs(kr), (name, sid, kg, kr)
+    fg, fr = sim.field_energy(), ref.field_energy()
+    assert abs(fg - fr) <= 1e-6 * fr, (name, fg, fr)
+
+
+def test_fp32_overflowing_velocity_raises_nonfinite_flag(oracle):
+    from paper_2501_07465_amd import pic
+    w = _small("disk2d", fp64=False)
+    ref = oracle.build_workload(w)
+    st = ref.state()
+    x, v, xi, wt = st[0]
+    v = v.copy()
+    v[5] = [1e39, 0.0, 0.0]  # finite in FP64, infinite in FP32
+    st[0] = (x, v, xi, wt)
+    print("case nonfinite flag", flush=True)
+    sim = pic.Simulation(w, precision="fp32", states=st, fields=ref.fields(), graphs=False)
+    assert sim.nonfinite() == 0
+    sim.step(3)
+    assert sim.nonfinite() == 1
+    xg, vg, _ = sim.particles(0)
+    assert np.all(np.isfinite(xg)) and np.all(np.isfinite(vg))
+    # the particle was held at rest; the others moved on
+    assert np.count_nonzero(np.all(vg == 0.0, axis=1)) >= 1
+    e, b = sim.fields()
+    assert np.all(np.isfinite(e)) and np.all(np.isfinite(b))
+    assert np.isfinite(sim.field_energy())
+    # a non-finite field value is refused at load
+    e[0, 0, 3, 3] = np.nan
+    with pytest.raises(pic.PicError) as ei:
+        pic.pic_load_fields(sim.h, e, None)
+    assert ei.value.code == pic.PIC_EINVAL

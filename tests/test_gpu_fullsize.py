@@ -43,7 +43,7 @@ def _inside(sp, X):
     return True
 
 
-@pytest.mark.parametrize("name", ["disk2d", "sheet2d"])
+@pytest.mark.parametrize("name", ["disk2d", "sheet2d", "sphere3d"])
 def test_fullsize_sampled_push_matches_oracle(oracle, name):
     from paper_2501_07465_amd import pic
     w, block = _bench_config(name)
@@ -102,17 +102,23 @@ def test_fullsize_sampled_push_matches_oracle(oracle, name):
             assert exi <= 1e-5, (name, sid, exi)
 
 
-def test_fullsize_keys_match_oracle_key(oracle):
-    """Every device key of the full disk equals the oracle's tile-major key of the same cell."""
+@pytest.mark.parametrize("name,sample", [("disk2d", 0), ("sphere3d", 400000)])
+def test_fullsize_keys_match_oracle_key(oracle, name, sample):
+    """Every device key of the full disk (a seeded sample of the sphere's) equals the oracle's
+    tile-major key of the same cell."""
     from paper_2501_07465_amd import pic
-    w, block = _bench_config("disk2d")
-    print("case full-size keys disk2d", flush=True)
+    w, block = _bench_config(name)
+    print(f"case full-size keys {name}", flush=True)
     sim = pic.Simulation(w, precision="fp32", graphs=True, block=block, series_cap=64)
     sim.step(25)
     dx = np.array(w["dx"])
+    rng = np.random.default_rng(5)
     for sid, sp in enumerate(w["species"]):
         x, v, xi = sim.particles(sid)
         keys = sim.keys(sid)
+        if sample and sample < len(x):
+            idx = np.sort(rng.choice(len(x), size=sample, replace=False))
+            x, v, xi, keys = x[idx], v[idx], xi[idx], keys[idx]
         X = x[:, :w["dims"]] / dx[:w["dims"]]
         # positions within 1e-6 of a cell face are ambiguous after the metre round trip: skip them
         frac = X - np.floor(X)
@@ -127,12 +133,13 @@ def test_fullsize_keys_match_oracle_key(oracle):
         assert np.array_equal(keys[ok], want)
 
 
-def test_fullsize_continuity_at_fp32_roundoff():
+@pytest.mark.parametrize("name", ["disk2d", "sphere3d"])
+def test_fullsize_continuity_at_fp32_roundoff(name):
     """The charge-conserving deposit at full size, bench configuration: the continuity residual (FP64
     diagnostic over FP32 positions and currents) stays at FP32 round-off of the current scale."""
     from paper_2501_07465_amd import pic
-    w, block = _bench_config("disk2d")
-    print("case full-size continuity disk2d", flush=True)
+    w, block = _bench_config(name)
+    print(f"case full-size continuity {name}", flush=True)
     sim = pic.Simulation(w, precision="fp32", graphs=False, block=block, track_continuity=True, series_cap=64)
     worst = 0.0
     for _ in range(3):
