@@ -1,6 +1,6 @@
 """Autotuner for the particle tile and the particle-kernel block size.
 
-The tile sets the LDS window of a particle block (E, B on T + 4 nodes per axis, J on T + 5) and
+The tile sets the LDS window of a particle block (E, B on T + 4 nodes per axis, J on T + 3) and
 the halo overhead; the unit (particles per block) splits a tile's particles over several blocks,
 each with its own current slot, so that a few dense tiles still spread over every compute unit;
 the block size sets how many wavefronts share one unit.  The best choice depends on the particle
@@ -34,12 +34,16 @@ STRAY_SCRATCH = 48  # values of LDS scratch per wavefront in the particle kernel
 
 
 def lds_bytes(tile, dims: int, precision: str, block: int = 512) -> int:
+    """LDS of a particle workgroup: E, B window (T + 4 per axis) and the stray scratch as reals,
+    then the current window (T + 3 per axis) as FP64 words (one per component; two in FP64)."""
     es = 8 if precision == "fp64" else 4
     vf = vj = 1
     for a in range(dims):
         vf *= tile[a] + 4
-        vj *= tile[a] + 5
-    return es * (6 * vf + 3 * vj + STRAY_SCRATCH * (block // 64))
+        vj *= tile[a] + 3
+    f = es * (6 * vf + STRAY_SCRATCH * (block // 64))
+    f = (f + 7) // 8 * 8
+    return f + 8 * (2 if precision == "fp64" else 1) * 3 * vj
 
 
 def candidates(w: dict, precision: str):

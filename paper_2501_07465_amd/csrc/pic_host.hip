@@ -183,7 +183,7 @@ static int setup_grid(pic_sim* s)
                 return fail(s, PIC_EINVAL, "periodic axis %d too short for tile %d", a, h.T[a]);
         }
         h.Wf[a] = act ? h.T[a] + kGL + kGHf : 1;
-        h.Wj[a] = act ? h.T[a] + kGL + kGHj : 1;
+        h.Wj[a] = act ? h.T[a] + kJL + kJH : 1;
         h.gl[a] = act ? kGL : 0;
         h.dx[a] = g.dx[a];
         h.inv_dx[a] = 1.0 / g.dx[a];
@@ -207,7 +207,7 @@ static int setup_grid(pic_sim* s)
     s->passes = (bits + 7) / 8;
     h.Vf = h.Wf[0] * h.Wf[1] * h.Wf[2];
     h.Vj = h.Wj[0] * h.Wj[1] * h.Wj[2];
-    const size_t plds = (size_t)s->es * (6 * (size_t)h.Vf + 3 * (size_t)h.Vj + (size_t)kStrayScratch * (g.block / 64));
+    const size_t plds = particle_lds_bytes(g.precision == PIC_FP64, h.Vf, h.Vj, g.block);
     if (plds > 65536) return fail(s, PIC_EINVAL, "particle tile needs %zu bytes of LDS (> 64 KiB)", plds);
     // field tiles
     const int ft[3][3] = {{FieldTile<1>::X, FieldTile<1>::Y, FieldTile<1>::Z},
@@ -498,7 +498,8 @@ static size_t plan(pic_sim* s, char* base, bool assign)
         for (int c = 0; c < 3; ++c) h.E[k][c] = P.takeb(L * es);
         for (int c = 0; c < 3; ++c) h.B[k][c] = P.takeb(L * es);
     }
-    for (int p = 0; p < 2; ++p) h.J[p] = P.takeb(3 * L * es);
+    const size_t jw = s->g.precision == PIC_FP64 ? JWords<double>::n : JWords<float>::n;
+    for (int p = 0; p < 2; ++p) h.J[p] = P.take<double>(jw * 3 * L);
     h.fdirty = P.take<int>(2 * (size_t)h.nftiles);
     s->max_slots = count_slot_tiles(s);
     h.max_slots = s->max_slots;
@@ -611,6 +612,29 @@ static void mirror_species(pic_sim* s, int i)
     }
 }
 
+// Quantum of the current (see kJqBits): K is the smallest power of two at or above the largest
+// single deposit value of any species, |q| w / (dt x the transverse cell area) for a move of a whole
+// cell along an active axis, or |q| w c / (the cell area of the active axes) for the speed of light
+// along an invariant axis (1D: y, z; 2D: z).
+static void set_current_quantum(pic_sim* s)
+{
+    const pic_grid_desc& g = s->g;
+    double kmax = 0.0;
+    for (const auto& x : s->sp) {
+        const double qw = std::fabs(x.d.q * x.weight);
+        double area = 1.0;
+        for (int a = 0; a < g.dims; ++a) area *= g.dx[a];
+        for (int a = 0; a < 3; ++a) {
+            const double k = a < g.dims ? qw / (g.dt * area / g.dx[a]) : qw * kC / area;
+            kmax = std::max(kmax, k);
+        }
+    }
+    int e = 0;
+    if (kmax > 0.0 && std::isfinite(kmax)) e = (int)std::ceil(std::log2(kmax));
+    s->h.jq = std::ldexp(1.0, kJqBits - e);
+    s->h.jq_inv = std::ldexp(1.0, e - kJqBits);
+}
+
 static int upload_table(pic_sim* s)
 {
     for (size_t i = 0; i < s->sp.size(); ++i) mirror_species(s, (int)i);
@@ -682,6 +706,7 @@ extern "C" int pic_bind(pic_sim* s, void* dev_arena, size_t bytes, void* hip_str
     }
     s->einv_max = 1.0;
     s->eoff_max = 0.0;
+    set_current_quantum(s);
     int r = upload_table(s);
     if (r) return r;
     for (size_t i = 0; i < s->sp.size(); ++i) {

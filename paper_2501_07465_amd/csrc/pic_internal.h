@@ -27,9 +27,14 @@ enum Region { R_ALL = 0, R_BALL = 1, R_BOX = 2 };
 
 // Halo widths of the particle-tile windows (cells, per active axis).  A particle
 // may sit up to one cell outside its tile between sorts.  Gather reads nodes
-// c0-1..c0+1 of the start cell c0; the charge-conserving deposit writes nodes
-// c0-1..c0+2.  Hence the field window spans [lo-2, hi+2] and the current
-// window [lo-2, hi+3].
+// c0-1..c0+1 of the start cell c0, so the field window spans [lo-2, hi+2].  The
+// charge-conserving deposit writes nodes c0..c0+1 for a move inside its start
+// cell and c0-1..c0+2 for a move that leaves it; the current window spans
+// [lo-1, hi+2], which holds the in-cell moves of every particle of the window
+// and the cell-leaving moves of particles that start inside the tile.  The rare
+// cell-leaving moves of particles that start in the one-cell ring around the
+// tile add to the global current directly; with them the deposits of a tile
+// reach [lo-2, hi+3] (the reach the field kernel tests).
 // Per-wavefront LDS scratch of the particle kernel (values): the global gather of a particle
 // outside its tile window stages 6 components x 2^3 nodes there.
 constexpr int kStrayScratch = 48;
@@ -47,9 +52,29 @@ constexpr int kSweepRowsEps = 6;
 template <>
 struct FieldTile<3> { static constexpr int X = 16, Y = 8, Z = 4; };
 
-constexpr int kGL = 2;       // low-side halo of both windows
+constexpr int kGL = 2;       // low-side halo of the field window (and low reach of a tile's deposits)
 constexpr int kGHf = 2;      // high-side halo of the field window
-constexpr int kGHj = 3;      // high-side halo of the current window
+constexpr int kGHj = 3;      // high reach of a tile's deposits
+constexpr int kJL = 1;       // low-side halo of the current window
+constexpr int kJH = 2;       // high-side halo of the current window
+
+// The current is accumulated in quanta: every deposit value is rounded to a whole number of
+// quanta 1 / jq and added as an integer-valued FP64 number, so each sum is exact and the same in
+// any order of the additions (LDS and global atomics alike): a run, its replay and the same
+// simulation in a batch give bit-identical currents.  jq = 2^kJqBits / K with K the smallest
+// power of two at or above the largest single deposit value of the simulation (a charge moving a
+// whole cell per step, or at the speed of light along an invariant axis), so one value is at most
+// 2^kJqBits quanta and sums stay exact up to 2^(53 - kJqBits) such values per node.  The FP64 form
+// also keeps the fraction of each value below one quantum, in units of 2^-kJqLoBits quanta, in a
+// second word, so it adds the FP64 values exactly.
+constexpr int kJqBits = 36;
+constexpr int kJqLoBits = 40;
+template <typename R>
+struct JWords;
+template <>
+struct JWords<float> { static constexpr int n = 1; };
+template <>
+struct JWords<double> { static constexpr int n = 2; };
 
 struct SpeciesDev {
     int kind, reflect, region, sheet_normal;
@@ -110,8 +135,11 @@ struct SimDev {
     int unit_cap;          // most particles per unit (0: one unit per tile)
     int* sort_hist;        // radix-sort digit histogram scratch
     int* sort_part;        // radix-sort digit totals [8][256] (copies summed by the row scan)
-    void* J[2];            // [3][Lvol] J^{n+1/2} by step parity: every tile window's current is
-                           // added by atomics, particles outside their window add directly
+    double* J[2];          // [words][3][Lvol] J^{n+1/2} by step parity, in quanta (integer-valued
+                           // FP64; FP32 form one word, FP64 form two: quanta and their fraction in
+                           // units of 2^-kJqLoBits): every tile's current window is added by exact
+                           // atomics, deposits outside the windows add directly
+    double jq, jq_inv;     // quanta per unit of current density, and its inverse (powers of two)
     int* fdirty;           // [2][nftiles] field tiles whose owned nodes of J[p] hold deposits
     long long* over_stamp; // [2] step+1 of the last overflow per parity
     unsigned long long* over_count;
@@ -166,6 +194,16 @@ __host__ __device__ inline int cell_key(const SimDev& S, const int c[3])
     int loc = (((c[2] & (S.T[2] - 1)) << S.Tshift[1]) + (c[1] & (S.T[1] - 1))) << S.Tshift[0];
     loc += c[0] & (S.T[0] - 1);
     return (tid << (S.Tshift[0] + S.Tshift[1] + S.Tshift[2])) + loc;
+}
+
+// LDS bytes of a particle-kernel workgroup: the E, B window and the per-wavefront stray scratch
+// (reals), rounded up to 8 bytes, then the current window (FP64 words).
+inline size_t particle_lds_bytes(bool fp64, int vf, int vj, int block)
+{
+    const size_t es = fp64 ? 8 : 4;
+    size_t f = es * (6 * (size_t)vf + (size_t)kStrayScratch * (size_t)(block / 64));
+    f = (f + 7) / 8 * 8;
+    return f + 8 * (size_t)(fp64 ? JWords<double>::n : JWords<float>::n) * 3 * (size_t)vj;
 }
 
 // ---- launchers (defined in the kernel translation units) ---------------------------------------
