@@ -284,6 +284,17 @@ int pic_diag(pic_sim* s, int kind, int arg, double* out, size_t cap, size_t* n_o
  * PIC_EDEVICE. */
 int pic_energy_histogram(pic_sim* s, int sid, double e_max, int nbins, uint64_t* counts);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid it): pic_energy_histogram with its
+ * device counters in a static array of the library (4097 counts of 64 bits, one
+ * copy per GPU, held until the process ends) instead of the simulation's arena.
+ * Same arguments, results and errors as pic_energy_histogram; nbins beyond 4096
+ * is refused with PIC_EINVAL.  The call allocates nothing and clears the counters
+ * it uses; all calls on one GPU share them, so calls that overlap on one GPU
+ * (several host threads, several streams) race.  Synchronises the simulation's
+ * stream.  Errors: PIC_EINVAL, PIC_ESTATE, PIC_EDEVICE. */
+int pic_energy_histogram_static(pic_sim* s, int sid, double e_max, int nbins, uint64_t* counts);
+
 /* Run nsteps plain (non-graph) steps with HIP events recorded on the bound
  * stream around each launch and return average device times in milliseconds:
  * out[0] particle kernel, out[1] field kernel, out[2] one cell sort of all

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -70,6 +71,7 @@ struct pic_sim {
     double* cont = nullptr;  // last continuity residual [2]
     int batch_refs = 0;      // member of a batch
     SimDev* d_batch = nullptr;  // the member's entry in the batch table
+    int device = 0;          // the GPU current at pic_bind (the arena's and the stream's)
     double einv_max = 1.0;   // largest loaded inverse permittivity (1 for the unit tensor)
     double eoff_max = 0.0;   // largest row sum of |off-diagonal inverse permittivity|
 };
@@ -102,6 +104,8 @@ static int fail(pic_sim* s, int code, const char* fmt, ...)
 }
 
 static thread_local std::string g_create_err;
+
+static int scratch_address(pic_sim* s, int dev, unsigned long long** out);
 
 #define HIPCHK(sim, expr)                                                                           \
     do {                                                                                            \
@@ -691,7 +695,14 @@ extern "C" int pic_bind(pic_sim* s, void* dev_arena, size_t bytes, void* hip_str
     s->st = reinterpret_cast<hipStream_t>(hip_stream);
     plan(s, s->arena, true);
     int dev = 0, ncu = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
+    HIPCHK(s, hipGetDevice(&dev));
+    s->device = dev;
+    {
+        // the static histogram scratch of this GPU (looked up once per device, with it current)
+        unsigned long long* scr = nullptr;
+        if (int r = scratch_address(s, dev, &scr)) return r;
+    }
+    {
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
     }
@@ -1237,11 +1248,66 @@ extern "C" int pic_energy_histogram(pic_sim* s, int sid, double e_max, int nbins
     if (!counts) return fail(s, PIC_EINVAL, "null counts");
     HIPCHK(s, enqueue_fill(s->h.hist, sizeof(unsigned long long) * (size_t)(nbins + 1), s->st));
     if (s->sp[sid].n > 0) {
-        if (s->es == 4) HIPCHK(s, Launchers<float>::energy_hist(dtab(s), sid, e_max, nbins, s->st));
-        else HIPCHK(s, Launchers<double>::energy_hist(dtab(s), sid, e_max, nbins, s->st));
+        if (s->es == 4) HIPCHK(s, Launchers<float>::energy_hist(dtab(s), sid, e_max, nbins, s->h.hist, s->st));
+        else HIPCHK(s, Launchers<double>::energy_hist(dtab(s), sid, e_max, nbins, s->h.hist, s->st));
     }
     HIPCHK(s, hipMemcpyAsync(counts, s->h.hist, sizeof(unsigned long long) * (size_t)(nbins + 1),
                              hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return PIC_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Histogram counts in a static device array, for callers that cannot allocate device memory.
+// Each GPU the library runs on holds its own copy of `scratch` until the process ends; host code
+// uses the device address hipGetSymbolAddress returns for the GPU (looked up once per device, at
+// pic_bind, with that device current), never the array's name.  Every call on one GPU shares that
+// GPU's copy: it is cleared at the start of each call, and calls that overlap on one GPU race.
+// ---------------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned long long scratch[kMaxHistBins + 1];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// The device address of the current GPU's copy of scratch (dev is that GPU).
+static int scratch_address(pic_sim* s, int dev, unsigned long long** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(s, PIC_EDEVICE, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(s, PIC_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<unsigned long long*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return PIC_OK;
+}
+
+extern "C" int pic_energy_histogram_static(pic_sim* s, int sid, double e_max, int nbins, uint64_t* counts)
+{
+    if (!s) return PIC_EINVAL;
+    if (!s->bound) return fail(s, PIC_ESTATE, "bind first");
+    if (sid < 0 || sid >= (int)s->sp.size()) return fail(s, PIC_EINVAL, "species id");
+    if (nbins < 1 || nbins > kMaxHistBins)
+        return fail(s, PIC_EINVAL, "nbins must be 1 .. %d (the static scratch holds %d counts)", kMaxHistBins,
+                    kMaxHistBins + 1);
+    if (!(e_max > 0.0) || !std::isfinite(e_max)) return fail(s, PIC_EINVAL, "e_max must be positive");
+    if (!counts) return fail(s, PIC_EINVAL, "null counts");
+    unsigned long long* scr = nullptr;
+    if (int r = scratch_address(s, s->device, &scr)) return r;
+    // zero fill by kernel (no memset node if the caller captures the stream)
+    HIPCHK(s, enqueue_fill(scr, sizeof(unsigned long long) * (size_t)(nbins + 1), s->st));
+    if (s->sp[sid].n > 0) {
+        if (s->es == 4) HIPCHK(s, Launchers<float>::energy_hist(dtab(s), sid, e_max, nbins, scr, s->st));
+        else HIPCHK(s, Launchers<double>::energy_hist(dtab(s), sid, e_max, nbins, scr, s->st));
+    }
+    HIPCHK(s, hipMemcpyAsync(counts, scr, sizeof(unsigned long long) * (size_t)(nbins + 1), hipMemcpyDeviceToHost,
+                             s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     return PIC_OK;
 }

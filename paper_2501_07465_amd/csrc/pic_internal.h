@@ -243,7 +243,8 @@ struct Launchers {
     static hipError_t load(int dims, SimDev* dS, const LoadArgs& A, hipStream_t st);
     static hipError_t field_energy(const SimDev* dS, int par, double* part, int nb, hipStream_t st);
     static hipError_t kinetic(const SimDev* dS, int s, double* part, int nb, hipStream_t st);
-    static hipError_t energy_hist(const SimDev* dS, int s, double e_max, int nbins, hipStream_t st);
+    static hipError_t energy_hist(const SimDev* dS, int s, double e_max, int nbins, unsigned long long* counts,
+                                  hipStream_t st);
     static hipError_t rho(int dims, const SimDev* dS, double* rho, int nb, hipStream_t st);
     static hipError_t gauss(int dims, const SimDev* dS, int par, const double* rho, double* part, int nb, hipStream_t st);
     static hipError_t continuity(int dims, const SimDev* dS, double* part, int nb, hipStream_t st);

@@ -34,7 +34,7 @@ PIC_SRC_NONE, PIC_SRC_SHEET, PIC_SRC_POINT = 0, 1, 2
 
 EXPORTED = ["pic_create", "pic_init_species", "pic_footprint", "pic_bind", "pic_load_particles",
             "pic_load_fields", "pic_load_eps_inv", "pic_load_eps_offdiag", "pic_load_ext_field", "pic_field_shape", "pic_init_fields", "pic_step", "pic_use_graphs",
-            "pic_diag", "pic_energy_histogram", "pic_time_kernels", "pic_sync", "pic_species_count", "pic_last_error", "pic_destroy",
+            "pic_diag", "pic_energy_histogram", "pic_energy_histogram_static", "pic_time_kernels", "pic_sync", "pic_species_count", "pic_last_error", "pic_destroy",
             "pic_batch_footprint", "pic_batch_create", "pic_batch_add", "pic_batch_remove",
             "pic_batch_step", "pic_batch_size", "pic_batch_last_error", "pic_batch_destroy"]
 
@@ -88,6 +88,7 @@ def lib():
         L.pic_load_eps_offdiag.argtypes = [_VP, _D]
         L.pic_load_ext_field.argtypes = [_VP, _D]
         L.pic_energy_histogram.argtypes = [_VP, C.c_int, C.c_double, C.c_int, C.POINTER(C.c_uint64)]
+        L.pic_energy_histogram_static.argtypes = [_VP, C.c_int, C.c_double, C.c_int, C.POINTER(C.c_uint64)]
         L.pic_field_shape.argtypes = [_VP, C.POINTER(C.c_int)]
         L.pic_init_fields.argtypes = [_VP, C.c_int]
         L.pic_step.argtypes = [_VP, C.c_int]
@@ -185,6 +186,12 @@ def pic_load_ext_field(h, e):
 def pic_energy_histogram(h, sid, e_max, nbins):
     out = np.zeros(nbins + 1, dtype=np.uint64)
     _check(lib().pic_energy_histogram(h, sid, e_max, nbins, out.ctypes.data_as(C.POINTER(C.c_uint64))), h)
+    return out
+
+
+def pic_energy_histogram_static(h, sid, e_max, nbins):
+    out = np.zeros(nbins + 1, dtype=np.uint64)
+    _check(lib().pic_energy_histogram_static(h, sid, e_max, nbins, out.ctypes.data_as(C.POINTER(C.c_uint64))), h)
     return out
 
 
