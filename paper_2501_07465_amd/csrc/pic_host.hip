@@ -222,7 +222,10 @@ static int setup_grid(pic_sim* s)
     for (int a = 0; a < 3; ++a) {
         h.FT[a] = a < g.dims ? ft[g.dims - 1][a] : 1;
         if (g.dims == 2 && a == 1 && g.eps_cells) h.FT[a] = kSweepRowsEps;
-        h.nft[a] = (g.n[a] + h.FT[a] - 1) / h.FT[a];
+        // the 3D plane march takes row pairs over all L_y rows (the last pair shifted down to end at
+        // the last row), columns and plane chunks over the cells (the last one also owns node n)
+        const int span = (g.dims == 3 && a == 1) ? h.L[a] : g.n[a];
+        h.nft[a] = (span + h.FT[a] - 1) / h.FT[a];
         h.nftiles *= h.nft[a];
         h.Lvol *= h.L[a];
     }
@@ -233,7 +236,7 @@ static int setup_grid(pic_sim* s)
     {
         int ve = 1, vb = 1, vj = 1;
         for (int a = 0; a < g.dims; ++a) { ve *= h.FT[a] + 3; vb *= h.FT[a] + 2; vj *= h.FT[a] + 1; }
-        fl = g.dims == 2 ? 0 : 3 * (ve + vb + vj);  // E_n, B, J (E_{n+1} overwrites J); the 2D row sweep uses none
+        fl = g.dims == 1 ? 3 * (ve + vb + vj) : 0;  // E_n, B, J (E_{n+1} overwrites J); the 2D and 3D sweeps use none
     }
     s->field_lds = fl;
     h.dt = g.dt;
