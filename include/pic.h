@@ -305,6 +305,12 @@ int pic_time_kernels(pic_sim* s, int nsteps, double out[4]);
 /* Wait for all enqueued work.  Errors: PIC_EDEVICE. */
 int pic_sync(pic_sim* s);
 
+/* Move the simulation's later work to another HIP stream (on the same device):
+ * the new stream first waits for everything enqueued on the old one so far
+ * (an event; the host does not wait).  Not while the simulation is in a batch.
+ * Errors: PIC_EINVAL, PIC_ESTATE, PIC_EDEVICE. */
+int pic_set_stream(pic_sim* s, void* hip_stream);
+
 /* Number of particles of a species (host value). */
 long long pic_species_count(const pic_sim* s, int sid);
 
@@ -316,23 +322,36 @@ const char* pic_last_error(const pic_sim* s);
 void pic_destroy(pic_sim* s);
 
 /* ---- Batched form: many independent simulations advanced by the same
- * persistent kernels (one launch per phase for the whole batch), captured in a
- * HIP graph.  All members must share dims and precision.  Membership changes
- * rewrite device tables only. ---- */
+ * persistent kernels (one launch per phase for the whole batch).  The batch has
+ * max_sims fixed slots; one HIP graph per sort period holds the particle and
+ * field launches over every slot (an empty slot is passed over), and each
+ * member's sorts are a graph of its own, captured when it joins.  Joining and
+ * leaving write the member's table entry on the batch stream (the host does not
+ * wait); the step graph is captured again only when a joining member needs
+ * more than it was captured for (larger LDS windows or block, a kernel
+ * variant, or a full-tensor permittivity).  All members share dims, precision
+ * and sort period. ---- */
 typedef struct pic_batch pic_batch;
 
 /* Device bytes of the batch tables for up to max_sims members. */
 int pic_batch_footprint(int max_sims, int dims, size_t* bytes);
-/* Create a batch over a caller-owned device arena and stream. */
+/* Create a batch over a caller-owned device arena and a non-null stream. */
 int pic_batch_create(int max_sims, int dims, int precision, void* dev_arena, size_t bytes,
                      void* hip_stream, pic_batch** out);
-/* Add or remove a bound simulation.  A member must be at a multiple of its
- * sort period when added.  Errors: PIC_EINVAL, PIC_ESTATE, PIC_ENOMEM. */
+/* Add or remove a bound simulation (bound to the batch stream).  A member must
+ * be at a multiple of its sort period when added.  A removed simulation can be
+ * stepped, read or moved to another stream (pic_set_stream) on its own; its
+ * diagnostics wait only for its own work when it is moved first.  Errors:
+ * PIC_EINVAL, PIC_ESTATE, PIC_ENOMEM, PIC_EDEVICE. */
 int pic_batch_add(pic_batch* b, pic_sim* s);
 int pic_batch_remove(pic_batch* b, pic_sim* s);
-/* Advance every member by k steps (k a multiple of the members' common sort period). */
+/* Advance every member by k steps (k a multiple of the members' common sort
+ * period); only enqueues. */
 int pic_batch_step(pic_batch* b, int k);
 int pic_batch_size(const pic_batch* b);
+/* How many times the step graph has been captured (membership changes that
+ * the captured graph covers do not capture it again). */
+int pic_batch_captures(const pic_batch* b);
 const char* pic_batch_last_error(const pic_batch* b);
 void pic_batch_destroy(pic_batch* b);
 

@@ -71,6 +71,9 @@ struct pic_sim {
     double* cont = nullptr;  // last continuity residual [2]
     int batch_refs = 0;      // member of a batch
     SimDev* d_batch = nullptr;  // the member's entry in the batch table
+    int bslot = -1;          // its slot
+    hipGraphExec_t bsort = nullptr;  // its periodic sorts in the batch (against its entry)
+    pic_batch* owner = nullptr;      // the batch it is in
     int device = 0;          // the GPU current at pic_bind (the arena's and the stream's)
     double einv_max = 1.0;   // largest loaded inverse permittivity (1 for the unit tensor)
     double eoff_max = 0.0;   // largest row sum of |off-diagonal inverse permittivity|
@@ -79,16 +82,7 @@ struct pic_sim {
 // The device table the kernels of this simulation must read: its own, or its batch entry.
 static SimDev* dtab(pic_sim* s) { return s->batch_refs ? s->d_batch : s->d; }
 
-struct pic_batch {
-    int max_sims = 0, dims = 0, precision = 0;
-    SimDev* table = nullptr;  // device [max_sims]
-    hipStream_t st = nullptr;
-    std::vector<pic_sim*> members;
-    std::string err;
-    hipGraphExec_t gexec = nullptr;
-    int graph_k = 0;
-    bool dirty = true;
-};
+struct pic_batch;
 
 static int fail(pic_sim* s, int code, const char* fmt, ...)
 {
@@ -1460,26 +1454,105 @@ extern "C" const char* pic_last_error(const pic_sim* s)
     return s ? s->err.c_str() : g_create_err.c_str();
 }
 
+extern "C" int pic_set_stream(pic_sim* s, void* hip_stream)
+{
+    if (!s) return PIC_EINVAL;
+    if (!s->bound) return fail(s, PIC_ESTATE, "simulation is not bound");
+    if (s->batch_refs) return fail(s, PIC_ESTATE, "simulation is in a batch");
+    hipStream_t ns = reinterpret_cast<hipStream_t>(hip_stream);
+    if (ns == s->st) return PIC_OK;
+    // the new stream waits for everything enqueued on the old one so far
+    hipEvent_t ev = nullptr;
+    HIPCHK(s, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ev, s->st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ns, ev, 0);
+    (void)hipEventDestroy(ev);
+    HIPCHK(s, e);
+    s->st = ns;
+    return PIC_OK;
+}
+
 extern "C" void pic_destroy(pic_sim* s)
 {
     if (!s) return;
+    if (s->batch_refs && s->owner) (void)pic_batch_remove(s->owner, s);
     drop_graph(s);
     delete s;
 }
 
 // ---------------------------------------------------------------------------------------------
-// Batched form
+// Batched form, over fixed slots.  The step graph (sort_every x (one particle launch + one field
+// launch) over every slot of the table) is captured once; an empty slot holds an entry with no
+// tiles and no units, which the kernels pass over.  A member's sorts are captured into a graph of
+// its own when it joins.  Joining and leaving write one table entry on the batch stream, by a
+// kernel (the host never waits for the device), and the step graph is captured again only when a
+// joining member needs more than it was captured for: larger LDS windows or block, a kernel
+// variant, or the full-tensor passes of a member (whose launches the graph holds per slot).
 // ---------------------------------------------------------------------------------------------
+static_assert(sizeof(SimDev) % 4 == 0, "table entries are copied as 32-bit words");
+constexpr size_t kIdleBytes = 256;  // the counters an empty slot's entry points at
+
+__global__ void k_put_entry(SimDev* dst, SimDev v)
+{
+    const unsigned* src = reinterpret_cast<const unsigned*>(&v);
+    unsigned* d = reinterpret_cast<unsigned*>(dst);
+    for (int i = threadIdx.x; i < (int)(sizeof(SimDev) / 4); i += blockDim.x) d[i] = src[i];
+}
+
+// write a table entry on a stream (the entry travels as a kernel argument)
+static hipError_t put_entry(SimDev* dst, const SimDev& v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_put_entry, dim3(1), dim3(256), 0, st, dst, v);
+    return hipGetLastError();
+}
+
+struct pic_batch {
+    int max_sims = 0, dims = 0, precision = 0;
+    SimDev* table = nullptr;          // device [max_sims]
+    void* idle = nullptr;             // device: the counters of an empty slot's entry (zeroed)
+    hipStream_t st = nullptr;
+    std::vector<pic_sim*> slot;       // [max_sims]: the member in each slot, or null
+    int size = 0;
+    int period = 0;                   // the members' common sort period
+    int ncu = 256;
+    std::string err;
+    hipGraphExec_t gexec = nullptr;   // the step graph
+    int captures = 0;                 // how often the step graph was captured
+    // what the step graph was captured for
+    int g_vf = 0, g_vj = 0, g_block = 0, g_flds = 0;
+    bool g_eps = false, g_rare = false, g_ext = false;
+    std::vector<int> g_tensor;        // slots whose full-tensor passes it launches
+    // sort graphs of members that left, released once the work enqueued before their leaving is done
+    std::vector<std::pair<hipGraphExec_t, hipEvent_t>> retired;
+};
+
 static int bfail(pic_batch* b, int code, const char* msg)
 {
     if (b) b->err = msg;
     return code;
 }
 
+static SimDev idle_entry(const pic_batch* b)
+{
+    SimDev e{};
+    e.dims = b->dims;
+    e.precision = b->precision;
+    long long* w = reinterpret_cast<long long*>(b->idle);
+    e.n_units = reinterpret_cast<int*>(w);  // no units
+    e.step_p = w + 1;
+    e.step_f = w + 2;
+    return e;
+}
+
+static size_t batch_table_bytes(int max_sims)
+{
+    return (sizeof(SimDev) * (size_t)max_sims + kAlign - 1) / kAlign * kAlign;
+}
+
 extern "C" int pic_batch_footprint(int max_sims, int dims, size_t* bytes)
 {
     if (!bytes || max_sims < 1 || max_sims > MAX_BATCH || dims < 1 || dims > 3) return PIC_EINVAL;
-    *bytes = sizeof(SimDev) * (size_t)max_sims + kAlign;
+    *bytes = batch_table_bytes(max_sims) + kIdleBytes;
     return PIC_OK;
 }
 
@@ -1492,13 +1565,27 @@ extern "C" int pic_batch_create(int max_sims, int dims, int precision, void* dev
     if (pic_batch_footprint(max_sims, dims, &need)) return PIC_EINVAL;
     if (!dev_arena || bytes < need || reinterpret_cast<uintptr_t>(dev_arena) % kAlign) return PIC_ENOMEM;
     if (precision != PIC_FP32 && precision != PIC_FP64) return PIC_EINVAL;
+    if (!hip_stream) return PIC_EINVAL;  // a batch is captured into graphs: not the legacy stream
     pic_batch* b = new (std::nothrow) pic_batch();
     if (!b) return PIC_ENOMEM;
     b->max_sims = max_sims;
     b->dims = dims;
     b->precision = precision;
     b->table = reinterpret_cast<SimDev*>(dev_arena);
+    b->idle = reinterpret_cast<char*>(dev_arena) + batch_table_bytes(max_sims);
     b->st = reinterpret_cast<hipStream_t>(hip_stream);
+    b->slot.assign(max_sims, nullptr);
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+        b->ncu = v;
+    hipError_t e = enqueue_fill(b->idle, kIdleBytes, b->st);
+    const SimDev idle = idle_entry(b);
+    for (int i = 0; i < max_sims && e == hipSuccess; ++i) e = put_entry(b->table + i, idle, b->st);
+    if (e != hipSuccess) {
+        delete b;
+        return PIC_EDEVICE;
+    }
     *out = b;
     return PIC_OK;
 }
@@ -1511,163 +1598,217 @@ static void batch_drop_graph(pic_batch* b)
     }
 }
 
+// release the sort graphs of members that left once the device has passed their leaving
+static void batch_reap(pic_batch* b, bool wait)
+{
+    size_t k = 0;
+    for (auto& r : b->retired) {
+        if (wait || hipEventQuery(r.second) == hipSuccess) {
+            if (wait) (void)hipEventSynchronize(r.second);
+            (void)hipGraphExecDestroy(r.first);
+            (void)hipEventDestroy(r.second);
+        } else {
+            b->retired[k++] = r;
+        }
+    }
+    b->retired.resize(k);
+}
+
+// does the step graph cover member s (its windows, block, kernel variants, no tensor passes)?
+static bool graph_covers(const pic_batch* b, const pic_sim* s)
+{
+    return b->gexec && s->h.Vf <= b->g_vf && s->h.Vj <= b->g_vj && s->g.block <= b->g_block &&
+           s->field_lds <= b->g_flds && (!s->h.einv || b->g_eps) && (!has_rare(s) || b->g_rare) &&
+           (!has_extra(s) || b->g_ext) && !s->h.eoff;
+}
+
 extern "C" int pic_batch_add(pic_batch* b, pic_sim* s)
 {
     if (!b || !s) return PIC_EINVAL;
     if (!s->bound) return bfail(b, PIC_ESTATE, "simulation is not bound");
     if (s->batch_refs) return bfail(b, PIC_ESTATE, "simulation already in a batch");
-    if ((int)b->members.size() >= b->max_sims) return bfail(b, PIC_ENOMEM, "batch is full");
+    if (b->size >= b->max_sims) return bfail(b, PIC_ENOMEM, "batch is full");
     if (s->g.dims != b->dims || s->g.precision != b->precision) return bfail(b, PIC_EINVAL, "dims or precision differ");
-    if (!b->st) return bfail(b, PIC_EINVAL, "a batch needs a non-default stream");
-    if (!b->members.empty() && s->g.sort_every != b->members[0]->g.sort_every)
-        return bfail(b, PIC_EINVAL, "members must share the sort period");
+    if (b->size > 0 && s->g.sort_every != b->period) return bfail(b, PIC_EINVAL, "members must share the sort period");
     if (s->h.track) return bfail(b, PIC_EINVAL, "continuity tracking is not batched");
     if (s->step % s->g.sort_every != 0) return bfail(b, PIC_ESTATE, "member must be at a multiple of its sort period");
     if (s->st != b->st) return bfail(b, PIC_EINVAL, "member must be bound to the batch stream");
-    // first sort (bound species) outside the batch graph
+    int i = 0;
+    while (b->slot[i]) ++i;
+    // first sort (bound species) outside the member's sort graph, on its own table
     if (s->need_sort || [&] { for (auto& x : s->sp) if (!x.sorted_once) return true; return false; }()) {
         if (enqueue_sort_all(s, nullptr)) return bfail(b, PIC_EDEVICE, s->err.c_str());
     }
+    SimDev* entry = b->table + i;
+    for (size_t j = 0; j < s->sp.size(); ++j) mirror_species(s, (int)j);
+    if (put_entry(entry, s->h, b->st) != hipSuccess) return bfail(b, PIC_EDEVICE, "table entry write failed");
+    // the member's periodic sorts, captured against its slot's entry (the host parities are put back:
+    // each launch of the graph flips them)
+    std::vector<int> par, sorted;
+    for (auto& x : s->sp) par.push_back(x.parity);
+    if (hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return bfail(b, PIC_EDEVICE, "sort capture failed");
+    SimDev* own = s->d;
+    s->d = entry;
+    const int r = enqueue_sort_all(s, &sorted);
+    s->d = own;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(b->st, &graph);
+    for (size_t j = 0; j < s->sp.size(); ++j) s->sp[j].parity = par[j];
+    hipGraphExec_t gx = nullptr;
+    if (!r && e == hipSuccess) e = hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (r || e != hipSuccess) {
+        (void)put_entry(entry, idle_entry(b), b->st);
+        return bfail(b, PIC_EDEVICE, r ? s->err.c_str() : hipGetErrorString(e));
+    }
+    s->bsort = gx;
+    s->graph_species = sorted;
     s->batch_refs = 1;
-    s->d_batch = b->table + b->members.size();
-    b->members.push_back(s);
-    b->dirty = true;
+    s->d_batch = entry;
+    s->bslot = i;
+    s->owner = b;
+    b->slot[i] = s;
+    if (b->size++ == 0) b->period = s->g.sort_every;
+    if (!graph_covers(b, s)) batch_drop_graph(b);
     return PIC_OK;
 }
 
 extern "C" int pic_batch_remove(pic_batch* b, pic_sim* s)
 {
     if (!b || !s) return PIC_EINVAL;
-    auto it = std::find(b->members.begin(), b->members.end(), s);
-    if (it == b->members.end()) return bfail(b, PIC_EINVAL, "not a member");
-    if (hipStreamSynchronize(b->st) != hipSuccess) return bfail(b, PIC_EDEVICE, "sync failed");
-    b->members.erase(it);
+    if (!s->batch_refs || s->bslot < 0 || s->bslot >= b->max_sims || b->slot[s->bslot] != s)
+        return bfail(b, PIC_EINVAL, "not a member");
+    const int i = s->bslot;
+    if (put_entry(b->table + i, idle_entry(b), b->st) != hipSuccess) return bfail(b, PIC_EDEVICE, "table entry write failed");
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, b->st) != hipSuccess)
+        return bfail(b, PIC_EDEVICE, "event failed");
+    b->retired.push_back({s->bsort, ev});
+    s->bsort = nullptr;
+    b->slot[i] = nullptr;
+    --b->size;
+    if (s->h.eoff) batch_drop_graph(b);  // the graph launches this slot's tensor passes
     s->batch_refs = 0;
     s->d_batch = nullptr;
-    for (size_t i = 0; i < b->members.size(); ++i) b->members[i]->d_batch = b->table + i;
-    // bring the member's own table up to date with the batch copy (pointer parities)
-    upload_table(s);
-    b->dirty = true;
+    s->bslot = -1;
+    s->owner = nullptr;
+    // the member's own table from the host state (pointer parities), after its last batched step
+    for (size_t j = 0; j < s->sp.size(); ++j) mirror_species(s, (int)j);
+    if (put_entry(s->d, s->h, s->st) != hipSuccess) return bfail(b, PIC_EDEVICE, "table entry write failed");
+    batch_reap(b, false);
     return PIC_OK;
 }
 
-extern "C" int pic_batch_size(const pic_batch* b) { return b ? (int)b->members.size() : 0; }
+extern "C" int pic_batch_size(const pic_batch* b) { return b ? b->size : 0; }
+
+extern "C" int pic_batch_captures(const pic_batch* b) { return b ? b->captures : 0; }
 
 extern "C" const char* pic_batch_last_error(const pic_batch* b) { return b ? b->err.c_str() : ""; }
 
 extern "C" void pic_batch_destroy(pic_batch* b)
 {
     if (!b) return;
+    (void)hipStreamSynchronize(b->st);
     batch_drop_graph(b);
-    for (auto* s : b->members) s->batch_refs = 0;
+    batch_reap(b, true);
+    for (auto* s : b->slot) {
+        if (!s) continue;
+        if (s->bsort) (void)hipGraphExecDestroy(s->bsort);
+        s->bsort = nullptr;
+        s->batch_refs = 0;
+        s->d_batch = nullptr;
+        s->bslot = -1;
+        s->owner = nullptr;
+        for (size_t j = 0; j < s->sp.size(); ++j) mirror_species(s, (int)j);
+        (void)put_entry(s->d, s->h, s->st);
+    }
+    (void)hipStreamSynchronize(b->st);
     delete b;
 }
 
-// one batched period: per-member sorts, then sort_every x (one particle launch + one field launch
-// over the whole batch)
-static int batch_enqueue_period(pic_batch* b, std::vector<std::vector<int>>* sorted)
+// capture the step graph for the current members (with room for every slot)
+static int batch_capture(pic_batch* b)
 {
-    const int n = (int)b->members.size();
-    int max_vf = 1, max_vj = 1, lds = 1, pgrid = 1, ft = 0, block = 64;
-    bool eps = false, rare = false, ext = false;
-    for (int i = 0; i < n; ++i) {
-        pic_sim* s = b->members[i];
-        std::vector<int> mine;
-        // the member's sort kernels address the batch table entry
-        SimDev* keep = s->d;
-        s->d = b->table + i;
-        int r = enqueue_sort_all(s, &mine);
-        s->d = keep;
-        if (r) return bfail(b, r, s->err.c_str());
-        if (sorted) sorted->push_back(mine);
-        max_vf = std::max(max_vf, s->h.Vf);
-        max_vj = std::max(max_vj, s->h.Vj);
-        lds = std::max(lds, s->field_lds);
-        pgrid = std::max(pgrid, s->pgrid);
-        ft += s->h.nftiles;
-        block = std::max(block, s->g.block);
-        eps = eps || s->h.einv != nullptr;
-        rare = rare || has_rare(s);
-        ext = ext || has_extra(s);
+    batch_drop_graph(b);
+    b->g_vf = b->g_vj = 1;
+    b->g_block = 64;
+    b->g_flds = 1;
+    b->g_eps = b->g_rare = b->g_ext = false;
+    b->g_tensor.clear();
+    for (int i = 0; i < b->max_sims; ++i) {
+        const pic_sim* s = b->slot[i];
+        if (!s) continue;
+        b->g_vf = std::max(b->g_vf, s->h.Vf);
+        b->g_vj = std::max(b->g_vj, s->h.Vj);
+        b->g_block = std::max(b->g_block, s->g.block);
+        b->g_flds = std::max(b->g_flds, s->field_lds);
+        b->g_eps = b->g_eps || s->h.einv != nullptr;
+        b->g_rare = b->g_rare || has_rare(s);
+        b->g_ext = b->g_ext || has_extra(s);
+        if (s->h.eoff) b->g_tensor.push_back(i);
     }
     Launch L{};
     L.sims = b->table;
-    L.nsims = n;
-    L.max_vf = max_vf;
-    L.max_vj = max_vj;
-    L.pgrid = pgrid;
-    L.block = block;
-    L.ftiles_total = ft;
-    L.eps = eps;
-    L.rare = rare;
-    L.ext = ext;
+    L.nsims = b->max_sims;
+    L.max_vf = b->g_vf;
+    L.max_vj = b->g_vj;
+    L.pgrid = b->ncu * 8;             // enough blocks for a full batch; blocks without units return
+    L.block = b->g_block;
+    L.ftiles_total = 1 << 30;         // the largest field grid; tasks are taken in a loop
+    L.eps = b->g_eps;
+    L.rare = b->g_rare;
+    L.ext = b->g_ext;
     L.stream = b->st;
-    const int P = b->members[0]->g.sort_every;
-    for (int k = 0; k < P; ++k) {
-        hipError_t e;
-        const bool f32 = b->precision == PIC_FP32;
+    const bool f32 = b->precision == PIC_FP32;
+    if (hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return bfail(b, PIC_EDEVICE, "capture failed");
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < b->period && e == hipSuccess; ++k) {
         e = f32 ? Launchers<float>::particles(b->dims, L) : Launchers<double>::particles(b->dims, L);
         // members with a full tensor fold its off-diagonal part into their current first
-        for (int i = 0; i < n && e == hipSuccess; ++i) {
-            const pic_sim* s = b->members[i];
-            if (!s->h.eoff) continue;
+        for (int i : b->g_tensor) {
+            if (e != hipSuccess) break;
+            const pic_sim* s = b->slot[i];
             e = f32 ? Launchers<float>::tensor(b->dims, b->table + i, s->h.Lvol, b->st)
                     : Launchers<double>::tensor(b->dims, b->table + i, s->h.Lvol, b->st);
         }
-        if (e == hipSuccess) e = f32 ? Launchers<float>::fields(b->dims, L, lds) : Launchers<double>::fields(b->dims, L, lds);
-        if (e != hipSuccess) return bfail(b, PIC_EDEVICE, hipGetErrorString(e));
+        if (e == hipSuccess)
+            e = f32 ? Launchers<float>::fields(b->dims, L, b->g_flds) : Launchers<double>::fields(b->dims, L, b->g_flds);
     }
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b->st, &graph);
+    if (e == hipSuccess) e = ec;
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        b->gexec = nullptr;
+        return bfail(b, PIC_EDEVICE, hipGetErrorString(e));
+    }
+    ++b->captures;
     return PIC_OK;
 }
 
 extern "C" int pic_batch_step(pic_batch* b, int k)
 {
     if (!b) return PIC_EINVAL;
-    if (b->members.empty()) return PIC_OK;
-    const int P = b->members[0]->g.sort_every;
+    if (b->size == 0) return PIC_OK;
+    const int P = b->period;
     if (k % P) return bfail(b, PIC_EINVAL, "k must be a multiple of the sort period");
-    if (b->dirty) {
-        // rewrite the device table with the members' current descriptors
-        batch_drop_graph(b);
-        for (size_t i = 0; i < b->members.size(); ++i) {
-            pic_sim* s = b->members[i];
-            for (size_t j = 0; j < s->sp.size(); ++j) mirror_species(s, (int)j);
-            if (hipMemcpyAsync(b->table + i, &s->h, sizeof(SimDev), hipMemcpyHostToDevice, b->st) != hipSuccess)
-                return bfail(b, PIC_EDEVICE, "table upload failed");
-        }
-        if (hipStreamSynchronize(b->st) != hipSuccess) return bfail(b, PIC_EDEVICE, "sync failed");
-        b->dirty = false;
+    if (!b->gexec) {
+        const int r = batch_capture(b);
+        if (r) return r;
     }
     for (int it = 0; it < k / P; ++it) {
-        if (!b->gexec) {
-            std::vector<std::vector<int>> sorted;
-            std::vector<std::vector<int>> par;
-            for (auto* s : b->members) {
-                std::vector<int> p;
-                for (auto& x : s->sp) p.push_back(x.parity);
-                par.push_back(p);
-            }
-            if (hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal) != hipSuccess)
-                return bfail(b, PIC_EDEVICE, "capture failed");
-            int r = batch_enqueue_period(b, &sorted);
-            hipGraph_t graph = nullptr;
-            hipError_t e = hipStreamEndCapture(b->st, &graph);
-            for (size_t i = 0; i < b->members.size(); ++i)
-                for (size_t j = 0; j < b->members[i]->sp.size(); ++j) b->members[i]->sp[j].parity = par[i][j];
-            if (r) { if (graph) (void)hipGraphDestroy(graph); return r; }
-            if (e != hipSuccess) return bfail(b, PIC_EDEVICE, hipGetErrorString(e));
-            e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            if (e != hipSuccess) { b->gexec = nullptr; return bfail(b, PIC_EDEVICE, hipGetErrorString(e)); }
-            b->graph_k = 0;
-            // remember which species each member sorts inside the graph
-            for (size_t i = 0; i < b->members.size(); ++i) b->members[i]->graph_species = sorted[i];
+        for (auto* s : b->slot) {
+            if (!s) continue;
+            if (hipGraphLaunch(s->bsort, b->st) != hipSuccess) return bfail(b, PIC_EDEVICE, "sort graph launch failed");
+            for (int j : s->graph_species) s->sp[j].parity ^= 1;
         }
         if (hipGraphLaunch(b->gexec, b->st) != hipSuccess) return bfail(b, PIC_EDEVICE, "graph launch failed");
-        for (auto* s : b->members) {
-            for (int j : s->graph_species) s->sp[j].parity ^= 1;
-            s->step += P;
-        }
+        for (auto* s : b->slot)
+            if (s) s->step += P;
     }
+    batch_reap(b, false);
     return PIC_OK;
 }

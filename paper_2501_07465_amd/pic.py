@@ -34,9 +34,9 @@ PIC_SRC_NONE, PIC_SRC_SHEET, PIC_SRC_POINT = 0, 1, 2
 
 EXPORTED = ["pic_create", "pic_init_species", "pic_footprint", "pic_bind", "pic_load_particles",
             "pic_load_fields", "pic_load_eps_inv", "pic_load_eps_offdiag", "pic_load_ext_field", "pic_field_shape", "pic_init_fields", "pic_step", "pic_use_graphs",
-            "pic_diag", "pic_energy_histogram", "pic_energy_histogram_static", "pic_time_kernels", "pic_sync", "pic_species_count", "pic_last_error", "pic_destroy",
+            "pic_diag", "pic_energy_histogram", "pic_energy_histogram_static", "pic_time_kernels", "pic_sync", "pic_set_stream", "pic_species_count", "pic_last_error", "pic_destroy",
             "pic_batch_footprint", "pic_batch_create", "pic_batch_add", "pic_batch_remove",
-            "pic_batch_step", "pic_batch_size", "pic_batch_last_error", "pic_batch_destroy"]
+            "pic_batch_step", "pic_batch_size", "pic_batch_captures", "pic_batch_last_error", "pic_batch_destroy"]
 
 
 class GridDesc(C.Structure):
@@ -95,6 +95,7 @@ def lib():
         L.pic_use_graphs.argtypes = [_VP, C.c_int]
         L.pic_diag.argtypes = [_VP, C.c_int, C.c_int, _D, C.c_size_t, C.POINTER(C.c_size_t)]
         L.pic_sync.argtypes = [_VP]
+        L.pic_set_stream.argtypes = [_VP, _VP]
         L.pic_time_kernels.argtypes = [_VP, C.c_int, _D]
         L.pic_species_count.argtypes = [_VP, C.c_int]
         L.pic_species_count.restype = C.c_longlong
@@ -108,6 +109,7 @@ def lib():
         L.pic_batch_remove.argtypes = [_VP, _VP]
         L.pic_batch_step.argtypes = [_VP, C.c_int]
         L.pic_batch_size.argtypes = [_VP]
+        L.pic_batch_captures.argtypes = [_VP]
         L.pic_batch_last_error.argtypes = [_VP]
         L.pic_batch_last_error.restype = C.c_char_p
         L.pic_batch_destroy.argtypes = [_VP]
@@ -234,6 +236,10 @@ def pic_sync(h):
     _check(lib().pic_sync(h), h)
 
 
+def pic_set_stream(h, stream_ptr):
+    _check(lib().pic_set_stream(h, C.c_void_p(stream_ptr)), h)
+
+
 def pic_species_count(h, sid) -> int:
     return lib().pic_species_count(h, sid)
 
@@ -273,6 +279,10 @@ def pic_batch_step(b, k):
 
 def pic_batch_size(b) -> int:
     return lib().pic_batch_size(b)
+
+
+def pic_batch_captures(b) -> int:
+    return lib().pic_batch_captures(b)
 
 
 def pic_batch_destroy(b):
@@ -415,6 +425,11 @@ class Simulation:
     def sync(self):
         pic_sync(self.h)
 
+    def set_stream(self, stream):
+        """Enqueue later work on ``stream`` (a torch stream), ordered after the work so far."""
+        pic_set_stream(self.h, stream.cuda_stream)
+        self.stream = stream
+
     def count(self, sid):
         return pic_species_count(self.h, sid)
 
@@ -497,6 +512,11 @@ class Batch:
 
     def __len__(self):
         return pic_batch_size(self.b)
+
+    @property
+    def captures(self) -> int:
+        """How many times the step graph was captured."""
+        return pic_batch_captures(self.b)
 
     def __del__(self):
         if getattr(self, "b", None):

@@ -3,10 +3,12 @@
 Requests (workload dicts with an ``arrival`` time in seconds and a step count) are admitted in
 arrival order while a slot is free and the sum of the admitted simulations' device footprints
 stays within the HBM budget.  Admitted simulations keep their particle and field state resident
-in their own arenas and advance together: every sort period is one captured graph holding the
-members' sorts and, per step, one particle launch and one field launch over the whole batch.
-A request that has run its steps is retired (its diagnostics are read back) and its slot and
-memory go to the next arrivals, while the others keep running.
+in their own arenas and advance together in one batch of fixed slots: every sort period is the
+members' sort graphs and one captured step graph (per step, one particle launch and one field
+launch over all slots).  A request is built on a loading stream of its own (so building it never
+waits for the batch), joins the batch between two periods, and leaves it after its last period:
+its slot is free for the next arrival at once, while its diagnostics are read on a read-back stream
+that waits only for its own last period (an event), after which its memory is released.
 
 Latency is arrival -> result read back; throughput is the particle-steps of all finished requests
 over the span from the first arrival to the last result.
@@ -35,6 +37,7 @@ class Request:
         self.particles = 0
         self.result = None
         self.error = None
+        self.done_event = None
 
 
 class Server:
@@ -52,11 +55,25 @@ class Server:
         self.unit = unit
         self.max_ahead = max_ahead
         self.batch = self._make_batch(max_slots, dims, precision)
+        self.load_stream = self._make_stream()
+        self.read_stream = self._make_stream()
         self.used = 0
         self.active: list[Request] = []
+        self.leaving: collections.deque = collections.deque()
 
     def _make_batch(self, max_slots, dims, precision):
         return pic.Batch(max_slots, dims, precision)
+
+    def _make_stream(self):
+        import torch
+        return torch.cuda.Stream()
+
+    def _event_on(self, stream):
+        """An event after the work enqueued on ``stream`` so far."""
+        import torch
+        ev = torch.cuda.Event()
+        ev.record(stream)
+        return ev
 
     def _prepare(self, r: Request):
         w = r.w
@@ -69,17 +86,26 @@ class Server:
         r.footprint = pic.footprint_of(w, self.precision, self.block, series_cap=r.steps + 64, unit=self.unit)
 
     def _admit(self, r: Request, now: float):
-        r.sim = pic.Simulation(r.w, precision=self.precision, graphs=False, stream=self.batch.stream,
+        # built (loaded, first fields) on the loading stream, then moved behind the batch's work
+        r.sim = pic.Simulation(r.w, precision=self.precision, graphs=False, stream=self.load_stream,
                                block=self.block, series_cap=r.steps + 64, unit=self.unit)
         r.particles = sum(r.sim.count(s) for s in r.sim.species)
+        r.sim.set_stream(self.batch.stream)
         self.batch.add(r.sim)
         self.used += r.footprint
         r.t_admit = now
         self.active.append(r)
 
-    def _retire(self, r: Request, t0: float):
+    def _leave(self, r: Request):
+        """After its last period is enqueued: free the slot, move the read-back behind that period."""
+        self.batch.remove(r.sim)
+        r.sim.set_stream(self.read_stream)
+        r.done_event = self._event_on(self.read_stream)
+        self.active.remove(r)
+        self.leaving.append(r)
+
+    def _collect(self, r: Request, t0: float):
         sim = r.sim
-        self.batch.remove(sim)  # synchronizes the batch stream
         r.result = {
             "field_energy": sim.field_energy(),
             "kinetic_energy": [sim.kinetic_energy(s) for s in sim.species],
@@ -87,17 +113,18 @@ class Server:
             "steps": sim.steps_done,
         }
         r.t_done = time.perf_counter() - t0
-        self.active.remove(r)
         self.used -= r.footprint
         r.sim = None
         del sim
 
+    def _collect_ready(self, t0: float, wait: bool = False):
+        while self.leaving and (wait or self.leaving[0].done_event.query()):
+            self._collect(self.leaving.popleft(), t0)
+            wait = False
+
     def _record(self):
-        """An event after the work enqueued so far (bounds how far the host runs ahead)."""
-        import torch
-        ev = torch.cuda.Event()
-        ev.record(self.batch.stream)
-        return ev
+        """An event after the batch work enqueued so far (bounds how far the host runs ahead)."""
+        return self._event_on(self.batch.stream)
 
     def run(self, requests: list[Request], log=None) -> dict:
         """Serve ``requests`` (arrival times relative to the call); returns latency and throughput."""
@@ -107,26 +134,28 @@ class Server:
                 r.error = f"footprint {r.footprint} exceeds the HBM budget"
         pending = collections.deque(sorted((r for r in requests if r.error is None), key=lambda r: r.arrival))
         inflight = collections.deque()
+        captures0 = self.batch.captures
         t0 = time.perf_counter()
-        while pending or self.active:
+        while pending or self.active or self.leaving:
             now = time.perf_counter() - t0
+            self._collect_ready(t0)
             while (pending and pending[0].arrival <= now and len(self.active) < self.max_slots
                    and self.used + pending[0].footprint <= self.budget):
                 self._admit(pending.popleft(), now)
                 if log:
                     log(f"admit: {len(self.active)} active, {self.used / 2**30:.2f} GiB")
             if not self.active:
-                time.sleep(max(0.0, min(0.05, pending[0].arrival - now)))
+                if self.leaving:
+                    self._collect_ready(t0, wait=True)
+                elif pending:
+                    time.sleep(max(0.0, min(0.05, pending[0].arrival - now)))
                 continue
             self.batch.step(self.period)
             inflight.append(self._record())
             for r in self.active:
                 r.left -= self.period
-            done = [r for r in self.active if r.left <= 0]
-            for r in done:
-                self._retire(r, t0)
-            if done:
-                inflight.clear()
+            for r in [r for r in self.active if r.left <= 0]:
+                self._leave(r)
             while len(inflight) > self.max_ahead:
                 inflight.popleft().synchronize()
         served = [r for r in requests if r.result is not None]
@@ -144,6 +173,7 @@ class Server:
             "span_s": span,
             "particle_steps": psteps,
             "particle_steps_per_s": psteps / span,
+            "graph_captures": self.batch.captures - captures0,
         }
 
 

@@ -1,8 +1,13 @@
-"""Batched and served simulations give the same results as the same simulations run alone.
+"""Batched and served simulations give the same results as the same simulations run alone, and
+the FP32 batched and served forms match the FP64 oracle.
 
 FP64 batch: element by element within 1e-12 of the same simulations stepped alone (and of the
 oracle).  FP32 batch and serving mix: end-of-run field energy, kinetic energies and the spectrum
-of the total-current series within 1e-3 relative of the run alone.
+of the total-current series within 1e-3 relative of the run alone and of the FP64 oracle's run of
+the same request (its own loader; the FP32 form starts from the same draws rounded to FP32),
+including one served request of the stream at its full grid scale and full step count (against
+the FP64 form, itself checked against the oracle on that request).  Joining
+and leaving a batch rewrite table entries only: the step graph is captured once.
 """
 import numpy as np
 import pytest
@@ -41,6 +46,14 @@ def _compare_results(a, b, tol, label):
     print(f"{label}: field energy {ef:.2e}, kinetic {ek:.2e}, current spectrum {es:.2e}", flush=True)
     assert a["steps"] == b["steps"]
     assert ef <= tol and ek <= tol and es <= tol, (label, ef, ek, es)
+
+
+def _oracle_result(oracle, w):
+    ref = oracle.build_workload(w)
+    ref.step(int(w["steps"]))
+    return {"field_energy": ref.field_energy(),
+            "kinetic_energy": [ref.kinetic_energy(s) for s in range(len(w["species"]))],
+            "current_series": ref.current_series(), "steps": int(w["steps"])}
 
 
 def test_batch_fp64_matches_alone_and_oracle(oracle):
@@ -83,11 +96,12 @@ def test_batch_fp64_matches_alone_and_oracle(oracle):
     assert _rel(eg, er) < 1e-12
 
 
-def test_batch_fp32_member_joining_mid_run():
+def test_batch_fp32_member_joining_mid_run(oracle):
     from paper_2501_07465_amd import pic, serve
     ws = _uneven(3, 80)
     print("case batch fp32 join", flush=True)
     ref = [serve.run_alone(w, "fp32") for w in ws]
+    orc = [_oracle_result(oracle, w) for w in ws]
     batch = pic.Batch(4, 2, "fp32")
     sims = [pic.Simulation(w, precision="fp32", graphs=False, stream=batch.stream, block=512,
                            series_cap=w["steps"] + 64) for w in ws]
@@ -104,9 +118,49 @@ def test_batch_fp32_member_joining_mid_run():
         res = {"field_energy": s.field_energy(), "kinetic_energy": [s.kinetic_energy(k) for k in s.species],
                "current_series": s.current_series(), "steps": s.steps_done}
         _compare_results(res, ref[i], 1e-3, f"batch fp32 member {i}")
+        _compare_results(res, orc[i], 1e-3, f"batch fp32 member {i} vs fp64 oracle")
+    # membership changes the captured step graph covers (same tile and block) never capture it again
+    assert batch.captures == 1
 
 
-def test_serving_results_same_alone_and_in_mix():
+def test_batch_slots_reused_without_recapture():
+    """Members leave and others take their slots between periods: one capture, and every member's
+    result is bit-identical to its run alone (the current is accumulated exactly)."""
+    from paper_2501_07465_amd import pic
+    ws = _uneven(4, 60)
+    print("case batch slot reuse", flush=True)
+    alone = []
+    for w in ws:
+        a = pic.Simulation(w, precision="fp32", graphs=False, block=512)
+        a.step(60)
+        alone.append(a)
+    batch = pic.Batch(2, 2, "fp32")
+    sims = [pic.Simulation(w, precision="fp32", graphs=False, stream=batch.stream, block=512) for w in ws]
+    batch.add(sims[0])
+    batch.add(sims[1])
+    batch.step(20)
+    batch.remove(sims[0])
+    batch.add(sims[2])        # takes slot 0 while sims[1] is mid-run
+    batch.step(40)
+    batch.remove(sims[1])     # sims[1] is done
+    batch.add(sims[3])
+    batch.step(20)
+    batch.remove(sims[2])     # sims[2] is done
+    batch.step(40)
+    batch.remove(sims[3])
+    batch.add(sims[0])        # back in, 40 steps to go
+    batch.step(40)
+    batch.remove(sims[0])
+    assert batch.captures == 1 and len(batch) == 0
+    for i, (a, s) in enumerate(zip(alone, sims)):
+        assert s.steps_done == 60, (i, s.steps_done)
+        ea, ba = a.fields()
+        es, bs = s.fields()
+        assert np.array_equal(ea, es) and np.array_equal(ba, bs), i
+        assert np.array_equal(a.current_series(), s.current_series()), i
+
+
+def test_serving_results_same_alone_and_in_mix(oracle):
     from paper_2501_07465_amd import serve, workloads as W
     reqs = []
     for j in range(5):
@@ -116,6 +170,7 @@ def test_serving_results_same_alone_and_in_mix():
         reqs.append(serve.Request(j, w, arrival=0.02 * j))
     print("case serving mix", flush=True)
     ref = [serve.run_alone(r.w, "fp32") for r in reqs]
+    orc = [_oracle_result(oracle, r.w) for r in reqs]
     # a budget that holds about three of them at once: later arrivals wait for memory
     fps = []
     for r in reqs:
@@ -126,5 +181,40 @@ def test_serving_results_same_alone_and_in_mix():
     print(f"serving: {stats}", flush=True)
     assert stats["requests"] == len(reqs) and stats["rejected"] == 0
     assert stats["p99_s"] >= stats["p50_s"] > 0
-    for r, a in zip(reqs, ref):
+    assert stats["graph_captures"] <= 1
+    for r, a, o in zip(reqs, ref, orc):
         _compare_results(r.result, a, 1e-3, f"request {r.rid}")
+        _compare_results(r.result, o, 1e-3, f"request {r.rid} vs fp64 oracle")
+
+
+def test_fullscale_stream_request_served_fp32_matches_fp64(oracle):
+    """Request 51 of the stream at its full grid scale (208^2 cells, a slab, 1420 steps) served
+    beside two small requests.  Its whole FP32 run against the whole FP64 run of the same request
+    (end-of-run metrics within 1e-3), and that FP64 form against the oracle over the first 100 steps
+    of the same request at full scale (element by element within 1e-12; the oracle's whole run
+    takes minutes on one core)."""
+    from paper_2501_07465_amd import pic, serve, workloads as W
+    big = W.stream_request(51, scale=1.0)
+    assert big["n"][0] == 208 and big["steps"] == 1420
+    big["tile"] = [16, 8, 1]
+    reqs = [serve.Request(0, big, arrival=0.0)]
+    for j in range(2):
+        w = W.stream_request(j, scale=0.1)
+        w["steps"] = 200
+        w["tile"] = [16, 8, 1]
+        reqs.append(serve.Request(1 + j, w, arrival=0.01 * (j + 1)))
+    print("case full-scale stream request 51", flush=True)
+    srv = serve.Server(dims=2, precision="fp32", hbm_budget=8 << 30, max_slots=4)
+    stats = srv.run(reqs)
+    assert stats["requests"] == 3
+    r64 = serve.run_alone(big, "fp64")
+    _compare_results(reqs[0].result, r64, 1e-3, "request 51 (full scale) fp32 served vs fp64")
+    ref = oracle.build_workload(big)
+    sim = pic.Simulation(big, precision="fp64", states=ref.state(), fields=ref.fields(), graphs=False)
+    sim.step(100)
+    ref.step(100)
+    eg, bg = sim.fields()
+    er, br = ref.fields()
+    print(f"request 51 fp64 vs oracle, 100 steps: E {_rel(eg, er):.2e}, B {_rel(bg, br):.2e}", flush=True)
+    assert _rel(eg, er) < 1e-12 and _rel(bg, br) < 1e-12
+    assert _rel(sim.current_series(), ref.current_series()) < 1e-12

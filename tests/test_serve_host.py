@@ -19,6 +19,9 @@ class _FakeSim:
     def count(self, sid):
         return self.w["particles"]
 
+    def set_stream(self, stream):
+        self.stream = stream
+
     def field_energy(self):
         return float(self.w["seed"])
 
@@ -39,8 +42,9 @@ class _FakeSim:
 class _FakeBatch:
     def __init__(self):
         self.members = []
-        self.stream = None
+        self.stream = "batch"
         self.max_members = 0
+        self.captures = 0
 
     def add(self, s):
         self.members.append(s)
@@ -56,8 +60,18 @@ class _FakeBatch:
 
 
 class _Ev:
+    """Done after ``polls`` queries (a read-back that is not finished at once)."""
+    polls = 0
+
+    def __init__(self):
+        self.left = _Ev.polls
+
+    def query(self):
+        self.left -= 1
+        return self.left < 0
+
     def synchronize(self):
-        pass
+        self.left = -1
 
 
 @pytest.fixture
@@ -66,8 +80,10 @@ def server(monkeypatch):
     monkeypatch.setattr(serve.pic, "Simulation", _FakeSim)
     monkeypatch.setattr(serve.pic, "footprint_of", lambda w, *a, **k: w["fp"])
     monkeypatch.setattr(serve.Server, "_make_batch", lambda self, *a: _FakeBatch())
-    monkeypatch.setattr(serve.Server, "_record", lambda self: _Ev())
+    monkeypatch.setattr(serve.Server, "_make_stream", lambda self: "side")
+    monkeypatch.setattr(serve.Server, "_event_on", lambda self, st: _Ev())
     _FakeSim.live = _FakeSim.peak = 0
+    _Ev.polls = 0
     return serve
 
 
@@ -124,3 +140,19 @@ def test_steps_must_be_whole_periods(server):
     srv = serve.Server(dims=2, hbm_budget=100, max_slots=4)
     with pytest.raises(ValueError):
         srv.run([_req(serve, 0, fp=1, steps=30, arrival=0.0)])
+
+
+def test_slot_is_reused_before_the_read_back_finishes(server):
+    """A request leaves the batch after its last period; the next one takes the slot at once, while
+    the finished one is collected (and its memory released) only once its read-back event is done."""
+    serve = server
+    _Ev.polls = 3
+    reqs = [_req(serve, i, fp=1, steps=20, arrival=0.0) for i in range(4)]
+    srv = serve.Server(dims=2, hbm_budget=10**9, max_slots=1)
+    stats = srv.run(reqs)
+    assert stats["requests"] == 4 and srv.batch.max_members == 1
+    # request k + 1 joined before request k was collected
+    for a, b in zip(reqs, reqs[1:]):
+        assert b.t_admit <= a.t_done
+    assert all(r.sim is None for r in reqs) and srv.used == 0 and not srv.leaving
+    assert stats["graph_captures"] == 0
