@@ -252,11 +252,14 @@ def run_serve(n_req, scale, load, block, tile, budget_gib, slots, log, unit=None
     reqs = [serve.Request(j, copy.deepcopy(base[j]), float(arrivals[j])) for j in range(n_req)]
     log(f"bench: serving {n_req} requests at {lam:.1f}/s (capacity probe {cap:.3e} particle-steps/s)")
     st = srv.run(reqs)
-    return {"requests": st["requests"], "p50_s": st["p50_s"], "p99_s": st["p99_s"], "mean_s": st["mean_s"],
+    return {"requests": st["requests"], "rejected": st["rejected"], "p50_s": st["p50_s"], "p99_s": st["p99_s"],
+            "mean_s": st["mean_s"], "span_s": st["span_s"], "particle_steps": st["particle_steps"],
             "particle_steps_per_s": st["particle_steps_per_s"], "arrival_rate_hz": lam, "load": load,
             "capacity_probe": cap, "grid_scale": scale, "hbm_budget_gib": budget_gib, "slots": slots,
-            "requests_desc": "seeded 2D3V disk/rod/slab requests, grid side U[128,1024] x scale, 8-32 ppc "
-                             "free + 8-32 ppc bound, 500-4000 steps, FP32"}
+            "step_graph_captures": st["graph_captures"],
+            "requests_desc": f"{n_req} seeded 2D3V disk/rod/slab requests with Poisson arrivals, grid side "
+                             f"U[128,1024] x {scale:g}, 8-32 ppc free + 8-32 ppc bound, 500-4000 steps, FP32; "
+                             "latency is arrival to result read back"}
 
 
 def tuned(name, log, autotune_now=False):
@@ -350,10 +353,10 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the legs of the other optional physics (walls, barrier, Dirac mass, ribbon)")
     ap.add_argument("--variant-steps", type=int, default=400)
-    ap.add_argument("--serve-requests", type=int, default=48)
-    ap.add_argument("--serve-scale", type=float, default=0.25)
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-scale", type=float, default=1.0)
     ap.add_argument("--serve-load", type=float, default=0.75)
-    ap.add_argument("--serve-budget-gib", type=float, default=16.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--calib-mib", type=int, default=0,
                     help="also run a float32 elementwise copy of this many MiB 3 times (counter calibration)")
@@ -363,7 +366,7 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
-    from paper_2501_07465_amd import autotune, workloads as W
+    from paper_2501_07465_amd import autotune, pic, workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
     def log(m):
@@ -385,12 +388,21 @@ def main():
     # the timed steps start on a sort-period boundary, so whole periods replay captured graphs
     warmup = max(P, -(-args.warmup // P) * P)
     if args.calib_mib:
+        # counter calibration: torch's vectorized elementwise copy of calib_mib MiB, and the library's
+        # structure-of-arrays copy (8 float arrays, 4-byte accesses per lane, calib_mib MiB in total)
         a = torch.ones(args.calib_mib << 18, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         for _ in range(3):
             torch.mul(a, 1.0, out=b)
+        n8 = (args.calib_mib << 18) // 8
+        srcs = [a[k * n8:(k + 1) * n8] for k in range(8)]
+        dsts = [b[k * n8:(k + 1) * n8] for k in range(8)]
+        st = torch.cuda.current_stream().cuda_stream
+        for _ in range(3):
+            pic.pic_measure_soa_copy([x.data_ptr() for x in srcs], [x.data_ptr() for x in dsts], n8, st)
         torch.cuda.synchronize()
-        del a, b
+        assert torch.equal(a, b)
+        del a, b, srcs, dsts
     head = fp32_leg(w, block, args.steps, warmup, graphs, args.time_kernels, args.workload, log)
     npart, rate32 = head["npart"], head["rate"]
     log(f"bench: fp32 {rate32:.3e} particle-steps/s; fp64 {args.fp64_steps} steps")

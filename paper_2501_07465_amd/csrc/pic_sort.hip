@@ -8,6 +8,8 @@
 #include "pic_dpp.h"
 #include "pic_internal.h"
 #include "pic_sort.h"
+#include "pic.h"
+#include "pic_measure.h"
 
 namespace pic {
 
@@ -465,4 +467,41 @@ hipError_t enqueue_ion(SimDev* dS, const double* rho, int uniform, const double*
     return hipGetLastError();
 }
 
+// ---- measurement helper: a structure-of-arrays streaming copy of known size ----
+struct SoaPtrs {
+    const float* src[PIC_MEASURE_MAX_ARRAYS];
+    float* dst[PIC_MEASURE_MAX_ARRAYS];
+};
+
+__global__ void __launch_bounds__(256) k_measure_soa_copy(SoaPtrs p, int narrays, long long n)
+{
+    for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        float v[PIC_MEASURE_MAX_ARRAYS];
+#pragma unroll
+        for (int k = 0; k < PIC_MEASURE_MAX_ARRAYS; ++k)
+            if (k < narrays) v[k] = p.src[k][i];
+#pragma unroll
+        for (int k = 0; k < PIC_MEASURE_MAX_ARRAYS; ++k)
+            if (k < narrays) p.dst[k][i] = v[k];
+    }
+}
+
 }  // namespace pic
+
+extern "C" int pic_measure_soa_copy(const float* const* src, float* const* dst, int narrays, long long n,
+                                    void* hip_stream)
+{
+    if (!src || !dst || narrays < 1 || narrays > PIC_MEASURE_MAX_ARRAYS || n < 0) return PIC_EINVAL;
+    pic::SoaPtrs p{};
+    for (int k = 0; k < narrays; ++k) {
+        if (!src[k] || !dst[k]) return PIC_EINVAL;
+        p.src[k] = src[k];
+        p.dst[k] = dst[k];
+    }
+    if (n == 0) return PIC_OK;
+    const long long blocks = (n + 255) / 256;
+    const int grid = (int)(blocks < 8192 ? blocks : 8192);
+    hipLaunchKernelGGL(pic::k_measure_soa_copy, dim3(grid), dim3(256), 0, reinterpret_cast<hipStream_t>(hip_stream),
+                       p, narrays, n);
+    return hipGetLastError() == hipSuccess ? PIC_OK : PIC_EDEVICE;
+}

@@ -36,7 +36,8 @@ EXPORTED = ["pic_create", "pic_init_species", "pic_footprint", "pic_bind", "pic_
             "pic_load_fields", "pic_load_eps_inv", "pic_load_eps_offdiag", "pic_load_ext_field", "pic_field_shape", "pic_init_fields", "pic_step", "pic_use_graphs",
             "pic_diag", "pic_energy_histogram", "pic_energy_histogram_static", "pic_time_kernels", "pic_sync", "pic_set_stream", "pic_species_count", "pic_last_error", "pic_destroy",
             "pic_batch_footprint", "pic_batch_create", "pic_batch_add", "pic_batch_remove",
-            "pic_batch_step", "pic_batch_size", "pic_batch_captures", "pic_batch_last_error", "pic_batch_destroy"]
+            "pic_batch_step", "pic_batch_size", "pic_batch_captures", "pic_batch_last_error", "pic_batch_destroy",
+            "pic_measure_soa_copy"]
 
 
 class GridDesc(C.Structure):
@@ -114,6 +115,7 @@ def lib():
         L.pic_batch_last_error.restype = C.c_char_p
         L.pic_batch_destroy.argtypes = [_VP]
         L.pic_batch_destroy.restype = None
+        L.pic_measure_soa_copy.argtypes = [C.POINTER(_VP), C.POINTER(_VP), C.c_int, C.c_longlong, _VP]
         _lib = L
     return _lib
 
@@ -287,6 +289,13 @@ def pic_batch_captures(b) -> int:
 
 def pic_batch_destroy(b):
     lib().pic_batch_destroy(b)
+
+
+def pic_measure_soa_copy(src_ptrs, dst_ptrs, n, stream_ptr):
+    """Counter-calibration copy: dst[k][:n] = src[k][:n] for device float arrays (pointers)."""
+    k = len(src_ptrs)
+    S, D = (_VP * k)(*src_ptrs), (_VP * k)(*dst_ptrs)
+    _check(lib().pic_measure_soa_copy(S, D, k, n, C.c_void_p(stream_ptr)))
 
 
 # ---- workload dicts -> descriptors -----------------------------------------------------------------

@@ -5,9 +5,14 @@ Inputs are the CSV files rocprofv3 writes with ``--output-format csv``:
 ``*_kernel_stats.csv`` (from ``--kernel-trace --stats``) and ``*_counter_collection.csv`` (from
 ``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``, one counter per run; values in KiB per dispatch).
 
-The calibration kernel is the float32 elementwise multiply that ``bench.py --calib-mib M`` runs
-three times: it reads and writes exactly M MiB, so the factor M * 1024 / (KiB counted) turns the
-counted KiB of any kernel in the same run into bytes.
+Two calibration kernels run in the same process (``bench.py --calib-mib M``, three times each),
+each reading and writing exactly M MiB: torch's float32 elementwise multiply (wide vector
+accesses) and the library's structure-of-arrays copy ``k_measure_soa_copy`` (8 float arrays, one
+4-byte element of each per lane: the access pattern of the particle kernel).  The factor
+M * 1024 / (KiB counted) of a calibration kernel turns the counted KiB of a kernel into bytes; the
+summaries report the raw counted bytes, the bytes under each factor, and take the
+structure-of-arrays factor as the traffic (the two factors differing is itself the evidence that
+the counters' units depend on the access width).
 
     python -m paper_2501_07465_amd.profiling traffic --fetch DIR --write DIR --kernel NAME \
         --calib-mib M --out FILE --command "..."
@@ -25,6 +30,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CALIB_KERNEL = "elementwise"  # torch's vectorized elementwise kernel of the calibration multiply
+SOA_KERNEL = "k_measure_soa_copy"  # the library's structure-of-arrays calibration copy
 KERNEL_SOURCES = ("csrc/pic_kernels.inc", "csrc/pic_internal.h", "csrc/pic_k32.hip", "csrc/pic_k64.hip")
 
 
@@ -80,15 +86,24 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, calib_mib: float) -> di
     write = counter_per_dispatch(write_dir, "WRITE_SIZE")
     kf, kw = _match(fetch, kernel), _match(write, kernel)
     cf, cw = _match(fetch, CALIB_KERNEL), _match(write, CALIB_KERNEL)
+    sf, sw = _match(fetch, SOA_KERNEL), _match(write, SOA_KERNEL)
+    mean = lambda v: sum(v) / len(v)  # noqa: E731
     ref_kib = calib_mib * 1024.0
-    f_factor = ref_kib / (sum(cf) / len(cf))
-    w_factor = ref_kib / (sum(cw) / len(cw))
-    fetch_b = sum(kf) / len(kf) * 1024.0 * f_factor
-    write_b = sum(kw) / len(kw) * 1024.0 * w_factor
-    return {"kernel": kernel, "dispatches": len(kf), "fetch_kib": sum(kf) / len(kf), "write_kib": sum(kw) / len(kw),
-            "calib_fetch_kib": sum(cf) / len(cf), "calib_write_kib": sum(cw) / len(cw), "calib_mib": calib_mib,
-            "fetch_factor": f_factor, "write_factor": w_factor, "fetch_bytes": fetch_b, "write_bytes": write_b,
-            "traffic_bytes": fetch_b + write_b}
+    f_factor, w_factor = ref_kib / mean(cf), ref_kib / mean(cw)
+    sf_factor, sw_factor = ref_kib / mean(sf), ref_kib / mean(sw)
+    fetch_kib, write_kib = mean(kf), mean(kw)
+    fetch_b = fetch_kib * 1024.0 * sf_factor
+    write_b = write_kib * 1024.0 * sw_factor
+    return {"kernel": kernel, "dispatches": len(kf), "fetch_kib": fetch_kib, "write_kib": write_kib,
+            "raw_fetch_bytes": fetch_kib * 1024.0, "raw_write_bytes": write_kib * 1024.0,
+            "calib_mib": calib_mib,
+            "calib_fetch_kib": mean(cf), "calib_write_kib": mean(cw),
+            "fetch_factor": f_factor, "write_factor": w_factor,
+            "soa_calib_fetch_kib": mean(sf), "soa_calib_write_kib": mean(sw),
+            "soa_fetch_factor": sf_factor, "soa_write_factor": sw_factor,
+            "fetch_bytes_elementwise_factor": fetch_kib * 1024.0 * f_factor,
+            "write_bytes_elementwise_factor": write_kib * 1024.0 * w_factor,
+            "fetch_bytes": fetch_b, "write_bytes": write_b, "traffic_bytes": fetch_b + write_b}
 
 
 def counter_summary(run_dir: str, kernels: list[str]) -> dict:
@@ -152,8 +167,9 @@ def main():
             f.write(f"# HBM traffic per dispatch of {a.kernel} on {a.workload} (rocprofv3 FETCH_SIZE, WRITE_SIZE)\n")
             for c in a.command:
                 f.write(f"# command: {c}\n")
-            f.write("# calibration: float32 elementwise multiply reading and writing calib_mib MiB; "
-                    "factor = calib bytes / counted bytes\n")
+            f.write("# calibration: torch float32 elementwise multiply and the library's structure-of-arrays copy, "
+                    "each reading and writing calib_mib MiB; factor = calib bytes / counted bytes; "
+                    "fetch_bytes and write_bytes use the structure-of-arrays factors\n")
             f.write(f"workload = {a.workload}\ntile = {a.tile}\nblock = {a.block}\nunit = {a.unit}\n"
                     f"source_digest = {source_digest()}\n")
             for k, v in r.items():

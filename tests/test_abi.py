@@ -1,4 +1,4 @@
-"""The C ABI: every symbol declared in include/pic.h is exported by the built library, and
+"""The C ABI: every symbol declared in include/*.h is exported by the built library, and
 host-side validation (no device memory) rejects bad descriptors with the documented codes."""
 import os
 import re
@@ -10,9 +10,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "pic.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(pic_[a-z_]+)\s*\(", src)))
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for f in sorted(os.listdir(inc)):
+        if f.endswith(".h"):
+            src = re.sub(r"/\*.*?\*/", "", open(os.path.join(inc, f)).read(), flags=re.S)
+            names |= set(re.findall(r"\b(pic_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -225,3 +229,17 @@ def test_eps_inv_map_places_the_yee_nodes():
     # E_z at (i, j): i in {2, 3}, j in {1, 2}
     assert np.all(m[2, 0][m[2, 0] != 1.0] == 0.125)
     assert W.eps_inv_map(w) is None
+
+
+def test_measure_copy_validation():
+    """The counter-calibration copy rejects bad arguments on the host (no device work)."""
+    import ctypes as C
+    from paper_2501_07465_amd import pic
+    L = pic.lib()
+    P = C.c_void_p * 2
+    src, dst = P(1, 2), P(3, 4)
+    assert L.pic_measure_soa_copy(src, dst, 0, 10, None) == pic.PIC_EINVAL
+    assert L.pic_measure_soa_copy(src, dst, 17, 10, None) == pic.PIC_EINVAL
+    assert L.pic_measure_soa_copy(src, dst, 2, -1, None) == pic.PIC_EINVAL
+    assert L.pic_measure_soa_copy(P(1, None), dst, 2, 10, None) == pic.PIC_EINVAL
+    assert L.pic_measure_soa_copy(src, dst, 2, 0, None) == pic.PIC_OK  # nothing to copy: no launch
