@@ -50,7 +50,7 @@ struct FieldTile<2> { static constexpr int X = 61, Y = 5, Z = 1; };  // row-swee
 // load ring and is faster on taller tasks)
 constexpr int kSweepRowsEps = 6;
 template <>
-struct FieldTile<3> { static constexpr int X = 61, Y = 2, Z = 32; };  // plane-march task: 61 columns, 2 rows, 32 planes
+struct FieldTile<3> { static constexpr int X = 61, Y = 3, Z = 8; };  // plane-march task: 61 columns, 3 rows, 8 planes
 
 constexpr int kGL = 2;       // low-side halo of the field window (and low reach of a tile's deposits)
 constexpr int kGHf = 2;      // high-side halo of the field window
