@@ -160,10 +160,10 @@ def run_variants(w, block, kt, npart, value, args, graphs, log):
     return out
 
 
-def committed_traffic(workload, tile, block, unit):
+def committed_traffic(workload, tile, block, unit, kernel="k_particles"):
     """Traffic per launch from the committed counter summary, if it matches the current kernels."""
     from paper_2501_07465_amd import profiling
-    path = os.path.join(ROOT, "profiles", f"traffic_k_particles_{workload}.txt")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
     if not os.path.exists(path):
         return None
     t = profiling.read_traffic_file(path)
@@ -285,8 +285,12 @@ def fp32_leg(w, block, steps, warmup, graphs, time_kernels, label, log):
     for a in range(w["dims"]):
         ncells *= w["n"][a]
     es = 4
-    bytes_particle = particle_bytes_per_step(w, counts, es) + occ * (6 * es + 3 * es)
-    bytes_step = bytes_particle + ncells * 12 * es + occ * 3 * es
+    # particle kernel: the particle state, the staged E and B of the occupied cells, and the current
+    # window added into J (one FP64 word of quanta per component in the FP32 form)
+    bytes_particle = particle_bytes_per_step(w, counts, es) + occ * (6 * es + 3 * 8)
+    # field kernel: E and B read and written at every node; J read and cleared where deposits are
+    bytes_field = ncells * 12 * es + occ * 3 * 8 * 2
+    bytes_step = bytes_particle + bytes_field
     t_particle_ms = float(kt[0])
     achieved = bytes_particle / (t_particle_ms * 1e-3) / 1e9
     ms_step = dt / steps * 1e3
@@ -298,6 +302,12 @@ def fp32_leg(w, block, steps, warmup, graphs, time_kernels, label, log):
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": committed_traffic(w["name"], w["tile"][:w["dims"]], block, w.get("unit", 0)),
                      "kernel": f"k_particles<{w['dims']},float,false,false>", "bytes_per_launch": bytes_particle},
+        "field_roofline": {"bound": "hbm", "achieved": bytes_field / (float(kt[1]) * 1e-3) / 1e9,
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": bytes_field / (float(kt[1]) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                           "traffic": committed_traffic(w["name"], w["tile"][:w["dims"]], block, w.get("unit", 0),
+                                                        "k_fields"),
+                           "kernel": f"k_fields<{w['dims']},float,false>", "bytes_per_launch": bytes_field},
         "step_roofline": {"bytes_per_step": bytes_step, "achieved": step_gbs, "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS},
         "kernels_ms": {"particles": t_particle_ms, "fields": float(kt[1]), "sort_per_sort": float(kt[2]),
@@ -441,6 +451,7 @@ def main():
         "fp64": fp64,
         "kernels_ms": head["kernels_ms"],
         "roofline": head["roofline"],
+        "field_roofline": head["field_roofline"],
         "step_roofline": head["step_roofline"],
         "field_energy_end": head["field_energy_end"],
     }
@@ -452,7 +463,7 @@ def main():
                              "unit": "particle-steps/s", "steps": args.secondary_steps, "ms_per_step": sec["ms_step"],
                              "tile": wd["tile"][:wd["dims"]], "block": bd, "unit_particles": wd.get("unit", 0),
                              "kernels_ms": sec["kernels_ms"], "roofline": sec["roofline"],
-                             "step_roofline": sec["step_roofline"]}
+                             "field_roofline": sec["field_roofline"], "step_roofline": sec["step_roofline"]}
     if wd is not None and wd["name"] == "disk2d" and args.eps_inf > 0 and not args.no_diagonal:
         # the disk with a per-cell inverse permittivity (the metal's background eps inside the disk):
         # the dielectric variant of the field kernel reads 3 more values per node
@@ -461,7 +472,7 @@ def main():
         we = W.with_dielectric(wd, [args.eps_inf] * 3)
         log(f"bench: dielectric leg, eps {args.eps_inf} in {we['dielectric']['region']['kind']}")
         _, dte, kte, _ = run_gpu(we, "fp32", args.eps_steps, 20, graphs, args.time_kernels, bd)
-        f_bytes = ncd * 12 * es + occd * 3 * es + ncd * 3 * es
+        f_bytes = ncd * 12 * es + occd * 3 * 8 * 2 + ncd * 3 * es  # E, B; J read and cleared; eps^-1
         f_ms = float(kte[1])
         f_gbs = f_bytes / (f_ms * 1e-3) / 1e9
         line["dielectric"] = {
@@ -481,7 +492,7 @@ def main():
         nu, nfold = tensor_list_sizes(wt)
         log(f"bench: full-tensor leg, {nfold} folded nodes, {nu} update-term nodes")
         _, dtt, ktt, _ = run_gpu(wt, "fp32", args.eps_steps, 20, graphs, args.time_kernels, bd)
-        t_bytes = sec["ncells"] * 18 * es + nu * 12 * es + nfold * 18 * es
+        t_bytes = sec["ncells"] * 18 * es + sec["occ"] * 3 * 8 * 2 + nu * 12 * es + nfold * 18 * es
         t_ms = float(ktt[1])
         t_gbs = t_bytes / (t_ms * 1e-3) / 1e9
         line["tensor"] = {

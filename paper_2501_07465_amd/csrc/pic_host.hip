@@ -528,6 +528,7 @@ static size_t plan(pic_sim* s, char* base, bool assign)
     h.rho_ion = P.take<double>(L);
     h.rho_a = P.take<double>(L);
     h.rho_b = P.take<double>(L);
+    h.rho_lo = P.take<double>(L);
     h.jtrack = h.track ? P.takeb(3 * L * es) : nullptr;
     h.einv = s->g.eps_cells ? P.takeb(3 * L * es) : nullptr;
     h.eoff = s->g.eps_cells == 2 ? P.takeb(6 * L * es) : nullptr;
@@ -634,6 +635,14 @@ static void set_current_quantum(pic_sim* s)
     if (kmax > 0.0 && std::isfinite(kmax)) e = (int)std::ceil(std::log2(kmax));
     s->h.jq = std::ldexp(1.0, kJqBits - e);
     s->h.jq_inv = std::ldexp(1.0, e - kJqBits);
+    // charge density: the largest single contribution is |q| w / (cell volume of the active axes)
+    double rmax = 0.0, vol = 1.0;
+    for (int a = 0; a < g.dims; ++a) vol *= g.dx[a];
+    for (const auto& x : s->sp) rmax = std::max(rmax, std::fabs(x.d.q * x.weight) / vol);
+    int er = 0;
+    if (rmax > 0.0 && std::isfinite(rmax)) er = (int)std::ceil(std::log2(rmax));
+    s->h.rhoq = std::ldexp(1.0, kJqBits - er);
+    s->h.rhoq_inv = std::ldexp(1.0, er - kJqBits);
 }
 
 static int upload_table(pic_sim* s)
@@ -950,9 +959,12 @@ extern "C" int pic_load_ext_field(pic_sim* s, const double* e)
     return PIC_OK;
 }
 
+// charge density of the particles at the nodes, summed exactly (whole quanta and their fractions,
+// as the current): the same for any order of the additions
 static hipError_t launch_rho(pic_sim* s, double* rho)
 {
     hipError_t e = enqueue_fill(rho, sizeof(double) * (size_t)s->h.Lvol, s->st);
+    if (e == hipSuccess) e = enqueue_fill(s->h.rho_lo, sizeof(double) * (size_t)s->h.Lvol, s->st);
     if (e != hipSuccess) return e;
     if (s->g.precision == PIC_FP32) return Launchers<float>::rho(s->g.dims, dtab(s), rho, kDiagBlocks, s->st);
     return Launchers<double>::rho(s->g.dims, dtab(s), rho, kDiagBlocks, s->st);

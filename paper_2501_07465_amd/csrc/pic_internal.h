@@ -69,6 +69,10 @@ constexpr int kJH = 2;       // high-side halo of the current window
 // second word, so it adds the FP64 values exactly.
 constexpr int kJqBits = 36;
 constexpr int kJqLoBits = 40;
+constexpr double kJqLoScale = 0x1p40;  // 2^kJqLoBits
+static_assert(kJqLoScale == (double)(1ll << kJqLoBits), "fraction scale");
+// The particles' charge density (Gauss-law initialisation and residual) is summed the same way,
+// both words for both forms, with rhoq quanta per C/m^3 from the largest single contribution.
 template <typename R>
 struct JWords;
 template <>
@@ -166,6 +170,8 @@ struct SimDev {
     double* rho_ion;       // [Lvol]
     double* rho_a;         // [Lvol]
     double* rho_b;         // [Lvol]
+    double* rho_lo;        // [Lvol]: fraction words of the exact charge-density sum
+    double rhoq, rhoq_inv; // quanta of charge density per C/m^3, and its inverse (powers of two)
     double* red;           // reduction scratch
     unsigned long long* hist;  // [kMaxHistBins + 1] energy-histogram counts
     SpeciesDev sp[MAXSP];
