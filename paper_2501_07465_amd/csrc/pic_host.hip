@@ -216,8 +216,14 @@ static int setup_grid(pic_sim* s)
     for (int a = 0; a < 3; ++a) {
         h.FT[a] = a < g.dims ? ft[g.dims - 1][a] : 1;
         if (g.dims == 2 && a == 1 && g.eps_cells) h.FT[a] = kSweepRowsEps;
-        // the 3D plane march takes row pairs over all L_y rows (the last pair shifted down to end at
-        // the last row), columns and plane chunks over the cells (the last one also owns node n)
+        // the 3D plane march takes row groups over all L_y rows (the last group shifted down to end
+        // at the last row), columns and plane chunks over the cells (the last one also owns node n).
+        // On a small grid the plane chunks are shortened until there are enough tasks to keep
+        // several wavefronts per SIMD (each task's march is a chain of dependent plane loads), down
+        // to two planes.
+        if (g.dims == 3 && a == 2)
+            while (h.FT[2] > 2 && (long long)h.nft[0] * h.nft[1] * ((g.n[2] + h.FT[2] - 1) / h.FT[2]) < kFieldTasksMin)
+                h.FT[2] /= 2;
         const int span = (g.dims == 3 && a == 1) ? h.L[a] : g.n[a];
         h.nft[a] = (span + h.FT[a] - 1) / h.FT[a];
         h.nftiles *= h.nft[a];
@@ -1047,6 +1053,7 @@ static Launch make_launch(pic_sim* s)
     L.rare = has_rare(s);
     L.ext = has_extra(s);
     L.tensor_lvol = s->h.eoff ? s->h.Lvol : 0;
+    for (int a = 0; a < 3; ++a) L.tile[a] = s->h.T[a];
     L.stream = s->st;
     return L;
 }
@@ -1532,6 +1539,7 @@ struct pic_batch {
     int captures = 0;                 // how often the step graph was captured
     // what the step graph was captured for
     int g_vf = 0, g_vj = 0, g_block = 0, g_flds = 0;
+    int g_tile[3] = {0, 0, 0};        // the members' common particle tile (0: they differ)
     bool g_eps = false, g_rare = false, g_ext = false;
     std::vector<int> g_tensor;        // slots whose full-tensor passes it launches
     // sort graphs of members that left, released once the work enqueued before their leaving is done
@@ -1629,7 +1637,9 @@ static void batch_reap(pic_batch* b, bool wait)
 // does the step graph cover member s (its windows, block, kernel variants, no tensor passes)?
 static bool graph_covers(const pic_batch* b, const pic_sim* s)
 {
-    return b->gexec && s->h.Vf <= b->g_vf && s->h.Vj <= b->g_vj && s->g.block <= b->g_block &&
+    const bool tile_ok = b->g_tile[0] == 0 ||
+                         (b->g_tile[0] == s->h.T[0] && b->g_tile[1] == s->h.T[1] && b->g_tile[2] == s->h.T[2]);
+    return b->gexec && tile_ok && s->h.Vf <= b->g_vf && s->h.Vj <= b->g_vj && s->g.block <= b->g_block &&
            s->field_lds <= b->g_flds && (!s->h.einv || b->g_eps) && (!has_rare(s) || b->g_rare) &&
            (!has_extra(s) || b->g_ext) && !s->h.eoff;
 }
@@ -1748,9 +1758,15 @@ static int batch_capture(pic_batch* b)
     b->g_flds = 1;
     b->g_eps = b->g_rare = b->g_ext = false;
     b->g_tensor.clear();
+    bool first = true;
     for (int i = 0; i < b->max_sims; ++i) {
         const pic_sim* s = b->slot[i];
         if (!s) continue;
+        for (int a = 0; a < 3; ++a) {
+            if (first) b->g_tile[a] = s->h.T[a];
+            else if (b->g_tile[a] != s->h.T[a]) b->g_tile[0] = b->g_tile[1] = b->g_tile[2] = 0;
+        }
+        first = false;
         b->g_vf = std::max(b->g_vf, s->h.Vf);
         b->g_vj = std::max(b->g_vj, s->h.Vj);
         b->g_block = std::max(b->g_block, s->g.block);
@@ -1771,6 +1787,7 @@ static int batch_capture(pic_batch* b)
     L.eps = b->g_eps;
     L.rare = b->g_rare;
     L.ext = b->g_ext;
+    for (int a = 0; a < 3; ++a) L.tile[a] = b->g_tile[a];
     L.stream = b->st;
     const bool f32 = b->precision == PIC_FP32;
     if (hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal) != hipSuccess)

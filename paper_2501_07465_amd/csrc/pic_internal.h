@@ -51,6 +51,9 @@ struct FieldTile<2> { static constexpr int X = 61, Y = 5, Z = 1; };  // row-swee
 constexpr int kSweepRowsEps = 6;
 template <>
 struct FieldTile<3> { static constexpr int X = 61, Y = 3, Z = 8; };  // plane-march task: 61 columns, 3 rows, 8 planes
+// fewest plane-march tasks a grid is split into before its plane chunks are shortened (about two
+// wavefronts per SIMD of the 256 CUs)
+constexpr int kFieldTasksMin = 2048;
 
 constexpr int kGL = 2;       // low-side halo of the field window (and low reach of a tile's deposits)
 constexpr int kGHf = 2;      // high-side halo of the field window
@@ -225,6 +228,7 @@ struct Launch {
     bool ext;              // some member has a static external field or per-carrier Dirac mass
     long long tensor_lvol; // field nodes of a simulation with a full tensor (0: none; a batch launches
                            // each tensor member's passes itself, through Launchers::tensor)
+    int tile[3];           // the particle tile shape shared by every member (0 if they differ)
     hipStream_t stream;
 };
 

@@ -145,12 +145,16 @@ def test_sort_order_bit_exact(oracle):
         assert float(np.max(np.abs(xg - xr) / np.array(w["dx"]))) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["disk2d", "sheet2d", "sphere3d", "slab1d"])
-def test_fp32_one_step_push(oracle, name):
+@pytest.mark.parametrize("name,tile", [("disk2d", None), ("sheet2d", None), ("sphere3d", None), ("slab1d", None),
+                                       # the tile shapes compiled with constant window geometry
+                                       ("disk2d", [32, 32, 1]), ("sphere3d", [4, 4, 4])])
+def test_fp32_one_step_push(oracle, name, tile):
     """FP32 form, one step from identical inputs (FP64 values rounded to FP32) within 1e-6."""
     from paper_2501_07465_amd import pic
     w = _small(name, fp64=False)
-    print(f"case fp32 one step {name}", flush=True)
+    if tile is not None:
+        w["tile"] = list(tile)
+    print(f"case fp32 one step {name} tile {w.get('tile')}", flush=True)
     base = oracle.build_workload(w)
     base.step(3)  # a state with non-zero fields
     st32 = []
