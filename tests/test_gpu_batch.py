@@ -218,3 +218,44 @@ def test_fullscale_stream_request_served_fp32_matches_fp64(oracle):
     print(f"request 51 fp64 vs oracle, 100 steps: E {_rel(eg, er):.2e}, B {_rel(bg, br):.2e}", flush=True)
     assert _rel(eg, er) < 1e-12 and _rel(bg, br) < 1e-12
     assert _rel(sim.current_series(), ref.current_series()) < 1e-12
+
+
+def test_batch_mixed_tile_shapes():
+    """A member whose tile has constant window geometry (32 x 32) beside one with a 16 x 8 tile: the
+    step graph takes the kernel that reads each member's geometry, and is captured again when the
+    second shape joins.  The 16 x 8 member equals its run alone bit for bit; the 32 x 32 member ran
+    alone on the fixed-geometry kernel and here partly on the general one, whose FP32 contractions
+    may round differently, so it is held to 1e-5 of its fields' scale."""
+    from paper_2501_07465_amd import pic
+    ws = _uneven(2, 40)
+    ws[0]["tile"] = [32, 32, 1]
+    ws[1]["tile"] = [16, 8, 1]
+    print("case batch mixed tiles", flush=True)
+    alone = []
+    for w in ws:
+        a = pic.Simulation(w, precision="fp32", graphs=False, block=512)
+        a.step(40)
+        alone.append(a)
+    batch = pic.Batch(2, 2, "fp32")
+    sims = [pic.Simulation(w, precision="fp32", graphs=False, stream=batch.stream, block=512) for w in ws]
+    batch.add(sims[0])
+    batch.step(20)              # the fixed-geometry kernel
+    batch.add(sims[1])          # another tile shape: captured again with the general kernel
+    batch.step(20)
+    batch.remove(sims[0])
+    batch.step(20)
+    batch.remove(sims[1])
+    assert batch.captures == 2
+    for i, (a, s) in enumerate(zip(alone, sims)):
+        assert s.steps_done == 40
+        ea, ba = a.fields()
+        es, bs = s.fields()
+        if i == 1:
+            assert np.array_equal(ea, es) and np.array_equal(ba, bs), i
+            for sid in range(len(ws[i]["species"])):
+                xa, va, _ = a.particles(sid)
+                xs, vs, _ = s.particles(sid)
+                assert np.array_equal(xa, xs) and np.array_equal(va, vs), (i, sid)
+        else:
+            print(f"fixed-geometry member: E rel {_rel(es, ea):.2e}", flush=True)
+            assert _rel(es, ea) < 1e-5 and _rel(bs, ba) < 1e-5, i

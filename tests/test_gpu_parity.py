@@ -46,11 +46,16 @@ def _compare(sim, ref, w, tol, label):
     assert ee < tol and eb < tol, (label, ee, eb)
 
 
-@pytest.mark.parametrize("name,steps", [("slab1d", 60), ("disk2d", 40), ("sheet2d", 40), ("sphere3d", 20)])
-def test_fp64_matches_oracle_from_same_state(oracle, name, steps):
+@pytest.mark.parametrize("name,steps,tile", [("slab1d", 60, None), ("disk2d", 40, None), ("sheet2d", 40, None),
+                                            ("sphere3d", 20, None),
+                                            # the FP64 tile shape compiled with constant window geometry
+                                            ("sphere3d", 20, [4, 8, 4])])
+def test_fp64_matches_oracle_from_same_state(oracle, name, steps, tile):
     from paper_2501_07465_amd import pic
     w = _small(name)
-    print(f"case fp64 {name} {steps} steps", flush=True)
+    if tile is not None:
+        w["tile"] = list(tile)
+    print(f"case fp64 {name} {steps} steps tile {w.get('tile')}", flush=True)
     ref = oracle.build_workload(w)
     sim = pic.Simulation(w, precision="fp64", states=ref.state(), fields=ref.fields(), graphs=False)
     sim.step(steps)
