@@ -173,6 +173,33 @@ def committed_traffic(workload, tile, block, unit, kernel="k_particles"):
     return float(t["traffic_bytes"])
 
 
+def copy_ceiling(log):
+    """HBM bandwidth a plain streaming copy reaches on this GPU: the library's structure-of-arrays copy
+    (8 float arrays of 128 MiB each, read and written: 2 GiB moved per launch, far beyond the caches),
+    timed with HIP events over 10 launches."""
+    import torch
+    from paper_2501_07465_amd import pic
+    n = 32 << 20  # floats per array
+    src = [torch.ones(n, dtype=torch.float32, device="cuda") for _ in range(8)]
+    dst = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(8)]
+    st = torch.cuda.current_stream()
+    sp, dp = [x.data_ptr() for x in src], [x.data_ptr() for x in dst]
+    pic.pic_measure_soa_copy(sp, dp, n, st.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(10):
+        pic.pic_measure_soa_copy(sp, dp, n, st.cuda_stream)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    assert all(torch.equal(a, b) for a, b in zip(src, dst))
+    gbs = 2 * 8 * n * 4 / (ms * 1e-3) / 1e9
+    log(f"bench: copy ceiling {gbs:.0f} GB/s")
+    del src, dst
+    return {"achieved": gbs, "unit": "GB/s", "ms_per_launch": ms,
+            "kernel": "pic_measure_soa_copy: 8 float arrays x 128 MiB, read and written"}
+
+
 def sphere_twin(seed):
     """The 64^3 twin of the nanosphere: radius 25 cells, the same 8 + 8 ppc, species and cell size."""
     from paper_2501_07465_amd import workloads as W
@@ -252,11 +279,25 @@ def run_serve(n_req, scale, load, block, tile, budget_gib, slots, log, unit=None
     reqs = [serve.Request(j, copy.deepcopy(base[j]), float(arrivals[j])) for j in range(n_req)]
     log(f"bench: serving {n_req} requests at {lam:.1f}/s (capacity probe {cap:.3e} particle-steps/s)")
     st = srv.run(reqs)
+    # the stream's aggregate HBM roofline: every finished request's algorithmic bytes (its particles,
+    # E and B at every node, staging and current at its occupied cells) over the serving span
+    es = 4
+    total_bytes = 0.0
+    for r in reqs:
+        if r.result is None:
+            continue
+        ncells = r.w["n"][0] * r.w["n"][1]
+        occ = occupied_cells(r.w)
+        per_step = particle_bytes_per_step(r.w, r.counts, es) + occ * (6 * es + 3 * 8) + ncells * 12 * es + occ * 3 * 8 * 2
+        total_bytes += per_step * r.steps
+    agg = total_bytes / st["span_s"] / 1e9
     return {"requests": st["requests"], "rejected": st["rejected"], "p50_s": st["p50_s"], "p99_s": st["p99_s"],
             "mean_s": st["mean_s"], "span_s": st["span_s"], "particle_steps": st["particle_steps"],
             "particle_steps_per_s": st["particle_steps_per_s"], "arrival_rate_hz": lam, "load": load,
             "capacity_probe": cap, "grid_scale": scale, "hbm_budget_gib": budget_gib, "slots": slots,
             "step_graph_captures": st["graph_captures"],
+            "roofline": {"bound": "hbm", "achieved": agg, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": agg / HBM_PEAK_GBS,
+                         "bytes": total_bytes, "what": "algorithmic bytes of all finished requests over the serving span"},
             "requests_desc": f"{n_req} seeded 2D3V disk/rod/slab requests with Poisson arrivals, grid side "
                              f"U[128,1024] x {scale:g}, 8-32 ppc free + 8-32 ppc bound, 500-4000 steps, FP32; "
                              "latency is arrival to result read back"}
@@ -455,6 +496,11 @@ def main():
         "step_roofline": head["step_roofline"],
         "field_energy_end": head["field_energy_end"],
     }
+    # the same kernels against what a plain streaming copy reaches on this GPU
+    ceiling = copy_ceiling(log)
+    line["copy_ceiling"] = ceiling
+    for k in ("roofline", "field_roofline"):
+        line[k]["copy_frac"] = line[k]["achieved"] / ceiling["achieved"]
     wd, bd = None, 256
     if args.secondary:
         wd, bd, _ = tuned(args.secondary, log)
@@ -508,9 +554,10 @@ def main():
     if wd is not None and wd["name"] == "disk2d" and not args.no_variants:
         line["variants"] = run_variants(wd, bd, sec["kt"], sec["npart"], sec["rate"], args, graphs, log)
     if args.serve_requests > 0:
+        # the disk's tuned tile, block and unit for every request of the stream
         line["serve"] = run_serve(args.serve_requests, args.serve_scale, args.serve_load, bd,
-                                  None, args.serve_budget_gib, args.serve_slots, log,
-                                  wd.get("unit", 0) if wd is not None else 0)
+                                  wd["tile"][:2] if wd is not None else None, args.serve_budget_gib,
+                                  args.serve_slots, log, wd.get("unit", 0) if wd is not None else 0)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, log)
     print(json.dumps(line))

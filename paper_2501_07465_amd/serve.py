@@ -35,6 +35,7 @@ class Request:
         self.t_admit = None
         self.t_done = None
         self.particles = 0
+        self.counts = []
         self.result = None
         self.error = None
         self.done_event = None
@@ -89,7 +90,8 @@ class Server:
         # built (loaded, first fields) on the loading stream, then moved behind the batch's work
         r.sim = pic.Simulation(r.w, precision=self.precision, graphs=False, stream=self.load_stream,
                                block=self.block, series_cap=r.steps + 64, unit=self.unit)
-        r.particles = sum(r.sim.count(s) for s in r.sim.species)
+        r.counts = [r.sim.count(s) for s in r.sim.species]
+        r.particles = sum(r.counts)
         r.sim.set_stream(self.batch.stream)
         self.batch.add(r.sim)
         self.used += r.footprint
