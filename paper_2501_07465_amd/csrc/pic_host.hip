@@ -220,9 +220,9 @@ static int setup_grid(pic_sim* s)
         // at the last row), columns and plane chunks over the cells (the last one also owns node n).
         // On a small grid the plane chunks are shortened until there are enough tasks to keep
         // several wavefronts per SIMD (each task's march is a chain of dependent plane loads), down
-        // to two planes.
+        // to two planes (one on grids of fewer than 32768 cells).
         if (g.dims == 3 && a == 2)
-            while (h.FT[2] > 2 && (long long)h.nft[0] * h.nft[1] * ((g.n[2] + h.FT[2] - 1) / h.FT[2]) < kFieldTasksMin)
+            while (h.FT[2] > ((long long)g.n[0] * g.n[1] * g.n[2] < 32768 ? 1 : 2) && (long long)h.nft[0] * h.nft[1] * ((g.n[2] + h.FT[2] - 1) / h.FT[2]) < kFieldTasksMin)
                 h.FT[2] /= 2;
         const int span = (g.dims == 3 && a == 1) ? h.L[a] : g.n[a];
         h.nft[a] = (span + h.FT[a] - 1) / h.FT[a];
