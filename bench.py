@@ -496,11 +496,13 @@ def main():
         "step_roofline": head["step_roofline"],
         "field_energy_end": head["field_energy_end"],
     }
-    # the same kernels against what a plain streaming copy reaches on this GPU
-    ceiling = copy_ceiling(log)
-    line["copy_ceiling"] = ceiling
-    for k in ("roofline", "field_roofline"):
-        line[k]["copy_frac"] = line[k]["achieved"] / ceiling["achieved"]
+    # the same kernels against what a plain streaming copy reaches on this GPU (not in the counter
+    # runs, whose calibration copies must be the only launches of that kernel)
+    if not args.calib_mib:
+        ceiling = copy_ceiling(log)
+        line["copy_ceiling"] = ceiling
+        for k in ("roofline", "field_roofline"):
+            line[k]["copy_frac"] = line[k]["achieved"] / ceiling["achieved"]
     wd, bd = None, 256
     if args.secondary:
         wd, bd, _ = tuned(args.secondary, log)

@@ -29,7 +29,7 @@ import hashlib
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-CALIB_KERNEL = "elementwise"  # torch's vectorized elementwise kernel of the calibration multiply
+CALIB_KERNEL = "MulFunctor"  # torch's vectorized elementwise kernel of the calibration multiply
 SOA_KERNEL = "k_measure_soa_copy"  # the library's structure-of-arrays calibration copy
 KERNEL_SOURCES = ("csrc/pic_kernels.inc", "csrc/pic_internal.h", "csrc/pic_k32.hip", "csrc/pic_k64.hip")
 
@@ -87,6 +87,10 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, calib_mib: float) -> di
     kf, kw = _match(fetch, kernel), _match(write, kernel)
     cf, cw = _match(fetch, CALIB_KERNEL), _match(write, CALIB_KERNEL)
     sf, sw = _match(fetch, SOA_KERNEL), _match(write, SOA_KERNEL)
+    for name, v in (("elementwise fetch", cf), ("elementwise write", cw), ("soa fetch", sf), ("soa write", sw)):
+        if max(v) > 1.1 * min(v):
+            raise ValueError(f"calibration dispatches of {name} disagree ({min(v)} .. {max(v)} KiB): "
+                             "another launch of the kernel ran in the counter run")
     mean = lambda v: sum(v) / len(v)  # noqa: E731
     ref_kib = calib_mib * 1024.0
     f_factor, w_factor = ref_kib / mean(cf), ref_kib / mean(cw)
