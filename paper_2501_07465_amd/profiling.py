@@ -11,13 +11,16 @@ accesses) and the library's structure-of-arrays copy ``k_measure_soa_copy`` (8 f
 4-byte element of each per lane: the access pattern of the particle kernel).  The factor
 M * 1024 / (KiB counted) of a calibration kernel turns the counted KiB of a kernel into bytes; the
 summaries report the raw counted bytes, the bytes under each factor, and take the
-structure-of-arrays factor as the traffic (the two factors differing is itself the evidence that
-the counters' units depend on the access width).
+structure-of-arrays factor as the traffic.  ``requests`` checks the factor: it counts the L2's read
+requests by size (32, 64 and 128 bytes) and its write requests (32 and 64 bytes), whose byte sums
+need no factor for a copy of known size.
 
     python -m paper_2501_07465_amd.profiling traffic --fetch DIR --write DIR --kernel NAME \
         --calib-mib M --out FILE --command "..."
     python -m paper_2501_07465_amd.profiling stats --trace DIR --out FILE --command "..."
     python -m paper_2501_07465_amd.profiling counters --run DIR --kernel NAME --out FILE --command "..."
+    python -m paper_2501_07465_amd.profiling requests --rd DIR --wr DIR --kernel NAME --calib-mib M \
+        --workload W --out FILE --command "..."
 """
 from __future__ import annotations
 
@@ -129,6 +132,36 @@ def counter_summary(run_dir: str, kernels: list[str]) -> dict:
     return out
 
 
+RD_COUNTERS = ("TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum")
+WR_COUNTERS = ("TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum")
+
+
+def request_bytes(rd_dir: str, wr_dir: str, kernels: list[str]) -> dict:
+    """Bytes the L2 requested from memory per dispatch, from the request counts by size: reads as
+    32 n_32 + 64 n_64 + 128 n_128 (and the share of each size), writes as 32 (n - n_64) + 64 n_64.
+    Counted this way a copy of known size needs no factor, so the result checks the calibrated
+    FETCH_SIZE and WRITE_SIZE figures."""
+    rd = {c: counter_per_dispatch(rd_dir, c) for c in RD_COUNTERS}
+    wr = {c: counter_per_dispatch(wr_dir, c) for c in WR_COUNTERS}
+    mean = lambda v: sum(v) / len(v)  # noqa: E731
+    out = {}
+    for k in kernels:
+        m = {c: mean(_match(rd[c], k)) for c in RD_COUNTERS}
+        w = {c: mean(_match(wr[c], k)) for c in WR_COUNTERS}
+        n = m["TCC_EA0_RDREQ_sum"]
+        sized = m["TCC_EA0_RDREQ_32B_sum"] + m["TCC_EA0_RDREQ_64B_sum"] + m["TCC_EA0_RDREQ_128B_sum"]
+        out[k] = {"dispatches": len(_match(rd["TCC_EA0_RDREQ_sum"], k)),
+                  "read_requests": n, "sized_fraction": sized / n if n else 0.0,
+                  "share_32B": m["TCC_EA0_RDREQ_32B_sum"] / n if n else 0.0,
+                  "share_64B": m["TCC_EA0_RDREQ_64B_sum"] / n if n else 0.0,
+                  "share_128B": m["TCC_EA0_RDREQ_128B_sum"] / n if n else 0.0,
+                  "read_bytes": 32 * m["TCC_EA0_RDREQ_32B_sum"] + 64 * m["TCC_EA0_RDREQ_64B_sum"]
+                  + 128 * m["TCC_EA0_RDREQ_128B_sum"],
+                  "write_bytes": 32 * (w["TCC_EA0_WRREQ_sum"] - w["TCC_EA0_WRREQ_64B_sum"])
+                  + 64 * w["TCC_EA0_WRREQ_64B_sum"]}
+    return out
+
+
 def read_traffic_file(path: str) -> dict:
     """key = value lines of a traffic summary (values as text)."""
     out = {}
@@ -159,6 +192,14 @@ def main():
     c.add_argument("--kernel", action="append", required=True)
     c.add_argument("--out", required=True)
     c.add_argument("--command", action="append", default=[])
+    q = sub.add_parser("requests")
+    q.add_argument("--rd", required=True)
+    q.add_argument("--wr", required=True)
+    q.add_argument("--kernel", action="append", required=True)
+    q.add_argument("--calib-mib", type=float, required=True)
+    q.add_argument("--workload", required=True)
+    q.add_argument("--out", required=True)
+    q.add_argument("--command", action="append", default=[])
     s = sub.add_parser("stats")
     s.add_argument("--trace", required=True)
     s.add_argument("--out", required=True)
@@ -178,6 +219,27 @@ def main():
                     f"source_digest = {source_digest()}\n")
             for k, v in r.items():
                 f.write(f"{k} = {v}\n")
+        print(open(a.out).read())
+    elif a.cmd == "requests":
+        ks = [CALIB_KERNEL, SOA_KERNEL] + a.kernel
+        r = request_bytes(a.rd, a.wr, ks)
+        ref = a.calib_mib * 1024.0 * 1024.0
+        with open(a.out, "w") as f:
+            f.write(f"# memory requests of the L2 by size on {a.workload}, average per dispatch "
+                    f"(rocprofv3 --pmc {' '.join(RD_COUNTERS)}, then {' '.join(WR_COUNTERS)})\n")
+            for c in a.command:
+                f.write(f"# command: {c}\n")
+            f.write(f"# read_bytes = 32 n_32B + 64 n_64B + 128 n_128B; write_bytes = 32 (n - n_64B) + 64 n_64B; "
+                    f"the calibration copies each read and write calib_mib = {a.calib_mib:g} MiB\n")
+            f.write(f"# source_digest = {source_digest()}\n")
+            for k, v in r.items():
+                f.write(f"\n[{k}] dispatches {v['dispatches']}\n")
+                for cn, cv in v.items():
+                    if cn != "dispatches":
+                        f.write(f"{cn} = {cv:.6g}\n")
+                if k in (CALIB_KERNEL, SOA_KERNEL):
+                    f.write(f"read_over_copy_size = {v['read_bytes'] / ref:.4f}\n"
+                            f"write_over_copy_size = {v['write_bytes'] / ref:.4f}\n")
         print(open(a.out).read())
     elif a.cmd == "counters":
         r = counter_summary(a.run, a.kernel)
