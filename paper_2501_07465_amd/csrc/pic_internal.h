@@ -147,7 +147,7 @@ struct SimDev {
                            // units of 2^-kJqLoBits): every tile's current window is added by exact
                            // atomics, deposits outside the windows add directly
     double jq, jq_inv;     // quanta per unit of current density, and its inverse (powers of two)
-    int* fdirty;           // [2][nftiles] field tiles whose owned nodes of J[p] hold deposits
+    int* fdirty;           // [2][nftiles] where the owned nodes of J[p] hold deposits: 1D tiles 0/1; 2D, 3D tasks a bit per particle-tile column (~0: all)
     long long* over_stamp; // [2] step+1 of the last overflow per parity
     unsigned long long* over_count;
     int* nonfinite;        // set to 1 by the particle kernel when a pushed velocity is not finite
