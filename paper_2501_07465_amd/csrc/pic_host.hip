@@ -189,11 +189,9 @@ static int setup_grid(pic_sim* s)
         h.mur_k[a] = (kC * g.dt - g.dx[a]) / (kC * g.dt + g.dx[a]);
     }
     // packed cell layout
-    const int sh[3][3] = {{0, 31, 31}, {0, 16, 31}, {0, 11, 22}};
-    const int mk[3][3] = {{0x7fffffff, 0, 0}, {0xffff, 0xffff, 0}, {0x7ff, 0x7ff, 0x3ff}};
     for (int a = 0; a < 3; ++a) {
-        h.pshift[a] = sh[g.dims - 1][a] >= 31 ? 0 : sh[g.dims - 1][a];
-        h.pmask[a] = mk[g.dims - 1][a];
+        h.pshift[a] = kCellShift[g.dims - 1][a];
+        h.pmask[a] = kCellMask[g.dims - 1][a];
     }
     long long tiles = 1;
     for (int a = 0; a < 3; ++a) tiles *= h.ntile[a];
@@ -1039,6 +1037,15 @@ static bool has_extra(const pic_sim* s)
     return false;
 }
 
+// the simulation's periodic active axes, a bit per axis (particle kernels are compiled for some masks)
+static int sim_permask(const pic_sim* s)
+{
+    int m = 0;
+    for (int a = 0; a < s->g.dims; ++a)
+        if (s->h.periodic[a]) m |= 1 << a;
+    return m;
+}
+
 static Launch make_launch(pic_sim* s)
 {
     Launch L{};
@@ -1054,6 +1061,7 @@ static Launch make_launch(pic_sim* s)
     L.ext = has_extra(s);
     L.tensor_lvol = s->h.eoff ? s->h.Lvol : 0;
     for (int a = 0; a < 3; ++a) L.tile[a] = s->h.T[a];
+    L.permask = sim_permask(s);
     L.stream = s->st;
     return L;
 }
@@ -1540,6 +1548,7 @@ struct pic_batch {
     // what the step graph was captured for
     int g_vf = 0, g_vj = 0, g_block = 0, g_flds = 0;
     int g_tile[3] = {0, 0, 0};        // the members' common particle tile (0: they differ)
+    int g_permask = -1;               // the members' common periodic active axes (-1: they differ)
     bool g_eps = false, g_rare = false, g_ext = false;
     std::vector<int> g_tensor;        // slots whose full-tensor passes it launches
     // sort graphs of members that left, released once the work enqueued before their leaving is done
@@ -1637,8 +1646,10 @@ static void batch_reap(pic_batch* b, bool wait)
 // does the step graph cover member s (its windows, block, kernel variants, no tensor passes)?
 static bool graph_covers(const pic_batch* b, const pic_sim* s)
 {
+    // a graph captured with a fixed-shape kernel takes members of that shape and periodic axes
     const bool tile_ok = b->g_tile[0] == 0 ||
-                         (b->g_tile[0] == s->h.T[0] && b->g_tile[1] == s->h.T[1] && b->g_tile[2] == s->h.T[2]);
+                         (b->g_tile[0] == s->h.T[0] && b->g_tile[1] == s->h.T[1] && b->g_tile[2] == s->h.T[2] &&
+                          (b->g_permask < 0 || b->g_permask == sim_permask(s)));
     return b->gexec && tile_ok && s->h.Vf <= b->g_vf && s->h.Vj <= b->g_vj && s->g.block <= b->g_block &&
            s->field_lds <= b->g_flds && (!s->h.einv || b->g_eps) && (!has_rare(s) || b->g_rare) &&
            (!has_extra(s) || b->g_ext) && !s->h.eoff;
@@ -1766,6 +1777,8 @@ static int batch_capture(pic_batch* b)
             if (first) b->g_tile[a] = s->h.T[a];
             else if (b->g_tile[a] != s->h.T[a]) b->g_tile[0] = b->g_tile[1] = b->g_tile[2] = 0;
         }
+        if (first) b->g_permask = sim_permask(s);
+        else if (b->g_permask != sim_permask(s)) b->g_permask = -1;
         first = false;
         b->g_vf = std::max(b->g_vf, s->h.Vf);
         b->g_vj = std::max(b->g_vj, s->h.Vj);
@@ -1788,6 +1801,7 @@ static int batch_capture(pic_batch* b)
     L.rare = b->g_rare;
     L.ext = b->g_ext;
     for (int a = 0; a < 3; ++a) L.tile[a] = b->g_tile[a];
+    L.permask = b->g_permask;
     L.stream = b->st;
     const bool f32 = b->precision == PIC_FP32;
     if (hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal) != hipSuccess)

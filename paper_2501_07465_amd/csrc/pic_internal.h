@@ -182,7 +182,29 @@ struct SimDev {
 
 // ---- small host/device helpers ----------------------------------------------------------------
 // Packed cell: the fields fill all 32 bits (2D: 16 + 16, 3D: 11 + 11 + 10), so packing and
-// unpacking run on unsigned values; the stored int is only ever unpacked, never compared.
+// unpacking run on unsigned values; the stored int is only ever unpacked, never compared.  The
+// layout depends only on the dimension: per dimension, the shift and the mask of each field.
+constexpr int kCellShift[3][3] = {{0, 0, 0}, {0, 16, 0}, {0, 11, 22}};
+constexpr int kCellMask[3][3] = {{0x7fffffff, 0, 0}, {0xffff, 0xffff, 0}, {0x7ff, 0x7ff, 0x3ff}};
+
+// the same with the dimension known at compile time (shifts and masks as immediates)
+template <int DIM>
+__host__ __device__ inline int pack_cell_d(int i, int j, int k)
+{
+    constexpr int s0 = kCellShift[DIM - 1][0], s1 = kCellShift[DIM - 1][1], s2 = kCellShift[DIM - 1][2];
+    return (int)(((unsigned)i << s0) | ((unsigned)j << s1) | ((unsigned)k << s2));
+}
+template <int DIM>
+__host__ __device__ inline void unpack_cell_d(int c, int out[3])
+{
+    constexpr int s0 = kCellShift[DIM - 1][0], s1 = kCellShift[DIM - 1][1], s2 = kCellShift[DIM - 1][2];
+    constexpr unsigned m0 = kCellMask[DIM - 1][0], m1 = kCellMask[DIM - 1][1], m2 = kCellMask[DIM - 1][2];
+    const unsigned u = (unsigned)c;
+    out[0] = (int)((u >> s0) & m0);
+    out[1] = (int)((u >> s1) & m1);
+    out[2] = (int)((u >> s2) & m2);
+}
+
 __host__ __device__ inline int pack_cell(const SimDev& S, int i, int j, int k)
 {
     return (int)(((unsigned)i << S.pshift[0]) | ((unsigned)j << S.pshift[1]) | ((unsigned)k << S.pshift[2]));
@@ -229,6 +251,7 @@ struct Launch {
     long long tensor_lvol; // field nodes of a simulation with a full tensor (0: none; a batch launches
                            // each tensor member's passes itself, through Launchers::tensor)
     int tile[3];           // the particle tile shape shared by every member (0 if they differ)
+    int permask;           // the members' periodic active axes, a bit per axis (-1 if they differ)
     hipStream_t stream;
 };
 

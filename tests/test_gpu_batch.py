@@ -220,6 +220,44 @@ def test_fullscale_stream_request_served_fp32_matches_fp64(oracle):
     assert _rel(sim.current_series(), ref.current_series()) < 1e-12
 
 
+def test_batch_members_of_one_shape_with_different_periodic_axes():
+    """Two members with the 32 x 32 tile, one periodic along y (the shape's kernel is compiled for
+    that axis) and one open on both axes: the step graph is captured again when the second joins,
+    with the kernel that reads the periodicity from the table.  The open member runs that kernel
+    alone too and equals its run alone bit for bit; the periodic one is held to 1e-5 of its fields'
+    scale (FP32 contractions of the two kernels may round differently)."""
+    from paper_2501_07465_amd import pic
+    ws = _uneven(2, 40)
+    for w in ws:
+        w["tile"] = [32, 32, 1]
+    ws[1]["periodic"] = [0, 0, 1]
+    print("case batch periodic masks", flush=True)
+    alone = []
+    for w in ws:
+        a = pic.Simulation(w, precision="fp32", graphs=False, block=512)
+        a.step(40)
+        alone.append(a)
+    batch = pic.Batch(2, 2, "fp32")
+    sims = [pic.Simulation(w, precision="fp32", graphs=False, stream=batch.stream, block=512) for w in ws]
+    batch.add(sims[0])
+    batch.step(20)
+    batch.add(sims[1])
+    batch.step(20)
+    batch.remove(sims[0])
+    batch.step(20)
+    batch.remove(sims[1])
+    assert batch.captures == 2
+    for i, (a, s) in enumerate(zip(alone, sims)):
+        assert s.steps_done == 40
+        ea, ba = a.fields()
+        es, bs = s.fields()
+        if i == 1:
+            assert np.array_equal(ea, es) and np.array_equal(ba, bs), i
+        else:
+            print(f"periodic-y member: E rel {_rel(es, ea):.2e}", flush=True)
+            assert _rel(es, ea) < 1e-5 and _rel(bs, ba) < 1e-5, i
+
+
 def test_batch_mixed_tile_shapes():
     """A member whose tile has constant window geometry (32 x 32) beside one with a 16 x 8 tile: the
     step graph takes the kernel that reads each member's geometry, and is captured again when the
