@@ -49,7 +49,11 @@ def _compare(sim, ref, w, tol, label):
 @pytest.mark.parametrize("name,steps,tile", [("slab1d", 60, None), ("disk2d", 40, None), ("sheet2d", 40, None),
                                             ("sphere3d", 20, None),
                                             # the FP64 tile shape compiled with constant window geometry
-                                            ("sphere3d", 20, [4, 8, 4])])
+                                            ("sphere3d", 20, [4, 8, 4]),
+                                            # tiles two cells wide: more tile columns reach a field
+                                            # task than its column mask has bits, so it reads J on
+                                            # every column
+                                            ("disk2d", 40, [2, 8, 1]), ("sphere3d", 20, [2, 4, 4])])
 def test_fp64_matches_oracle_from_same_state(oracle, name, steps, tile):
     from paper_2501_07465_amd import pic
     w = _small(name)
