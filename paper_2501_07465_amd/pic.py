@@ -420,13 +420,18 @@ class Simulation:
         pic_use_graphs(self.h, graphs)
 
     def __del__(self):
-        if getattr(self, "h", None):
-            try:
-                pic_sync(self.h)
-            except Exception:
-                pass
-            pic_destroy(self.h)
-            self.h = None
+        h = getattr(self, "h", None)
+        if not h:
+            return
+        self.h = None
+        try:
+            pic_sync(h)
+        except Exception:
+            pass
+        try:
+            pic_destroy(h)
+        except TypeError:
+            pass  # at interpreter exit this module's functions may already be gone; the process frees it
 
     def step(self, n=1):
         pic_step(self.h, n)
@@ -528,14 +533,19 @@ class Batch:
         return pic_batch_captures(self.b)
 
     def __del__(self):
-        if getattr(self, "b", None):
-            for s in list(getattr(self, "members", [])):
-                try:
-                    pic_batch_remove(self.b, s.h)
-                except Exception:
-                    pass
-            pic_batch_destroy(self.b)
-            self.b = None
+        b = getattr(self, "b", None)
+        if not b:
+            return
+        for s in list(getattr(self, "members", [])):
+            try:
+                pic_batch_remove(b, s.h)
+            except Exception:
+                pass
+        self.b = None
+        try:
+            pic_batch_destroy(b)
+        except TypeError:
+            pass  # at interpreter exit this module's functions may already be gone; the process frees it
 
 
 def footprint_of(w: dict, precision: str | None = None, block: int = 256, series_cap: int | None = None,
