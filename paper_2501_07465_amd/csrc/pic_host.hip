@@ -214,6 +214,7 @@ static int setup_grid(pic_sim* s)
     for (int a = 0; a < 3; ++a) {
         h.FT[a] = a < g.dims ? ft[g.dims - 1][a] : 1;
         if (g.dims == 2 && a == 1 && g.eps_cells) h.FT[a] = kSweepRowsEps;
+        if (g.dims == 3 && a == 1 && g.precision == PIC_FP64) h.FT[a] = kPlaneRowsFp64;
         // the 3D plane march takes row groups over all L_y rows (the last group shifted down to end
         // at the last row), columns and plane chunks over the cells (the last one also owns node n).
         // On a small grid the plane chunks are shortened until there are enough tasks to keep

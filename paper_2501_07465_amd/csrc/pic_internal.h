@@ -51,6 +51,9 @@ struct FieldTile<2> { static constexpr int X = 61, Y = 5, Z = 1; };  // row-swee
 constexpr int kSweepRowsEps = 6;
 template <>
 struct FieldTile<3> { static constexpr int X = 61, Y = 3, Z = 8; };  // plane-march task: 61 columns, 3 rows, 8 planes
+// rows of a plane-march task in the FP64 form (its slabs of doubles take twice the registers: with
+// three rows it held one wavefront per SIMD)
+constexpr int kPlaneRowsFp64 = 2;
 // fewest plane-march tasks a grid is split into before its plane chunks are shortened (about two
 // wavefronts per SIMD of the 256 CUs)
 constexpr int kFieldTasksMin = 2048;
