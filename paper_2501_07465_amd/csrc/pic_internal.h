@@ -50,7 +50,7 @@ struct FieldTile<2> { static constexpr int X = 61, Y = 5, Z = 1; };  // row-swee
 // load ring and is faster on taller tasks)
 constexpr int kSweepRowsEps = 6;
 template <>
-struct FieldTile<3> { static constexpr int X = 61, Y = 3, Z = 8; };  // plane-march task: 61 columns, 3 rows, 8 planes
+struct FieldTile<3> { static constexpr int X = 61, Y = 3, Z = 10; };  // plane-march task: 61 columns, 3 rows, 10 planes
 // rows of a plane-march task in the FP64 form (its slabs of doubles take twice the registers: with
 // three rows it held one wavefront per SIMD)
 constexpr int kPlaneRowsFp64 = 2;
