@@ -61,6 +61,8 @@ struct pic_sim {
     int es = 4;              // element size of reals
     int passes = 1;
     int pgrid = 1;
+    int ncu = 0;                 // compute units of the device at pic_bind
+    unsigned* pqueue = nullptr;  // the particle kernel's unit queue (in the arena, zeroed at bind)
     int field_lds = 0;
     int max_slots = 0;
     bool graphs = false;
@@ -542,6 +544,7 @@ static size_t plan(pic_sim* s, char* base, bool assign)
     h.tcount = s->g.eps_cells == 2 ? P.take<int>(2) : nullptr;
     h.eext = s->g.ext_field ? P.takeb(3 * L * es) : nullptr;
     h.red = P.take<double>(16);
+    s->pqueue = P.take<unsigned>(kUnitQueueWords);
     h.hist = P.take<unsigned long long>(kMaxHistBins + 1);
     s->part = P.take<double>(kDiagBlocks * 4);
     s->outv = P.take<double>(16);
@@ -717,8 +720,10 @@ extern "C" int pic_bind(pic_sim* s, void* dev_arena, size_t bytes, void* hip_str
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
     }
-    // persistent particle grid: a multiple of 8 (the XCD count) up to 8 workgroups per CU
+    // the largest particle grid: a multiple of 8 (the XCD count) up to 8 workgroups per CU; each launch
+    // fits it to the blocks its kernel can hold on the device at once
     s->pgrid = std::max(8, (std::min(s->h.max_units, ncu * 8) + 7) / 8 * 8);
+    s->ncu = ncu;
     HIPCHK(s, enqueue_fill(s->arena, need - kAlign, s->st));
     if (s->h.einv) {
         // the unit tensor until pic_load_eps_inv: 1.0f, or 1.0 as the words (0, 0x3ff00000)
@@ -1063,6 +1068,8 @@ static Launch make_launch(pic_sim* s)
     L.tensor_lvol = s->h.eoff ? s->h.Lvol : 0;
     for (int a = 0; a < 3; ++a) L.tile[a] = s->h.T[a];
     L.permask = sim_permask(s);
+    L.queue = s->pqueue;
+    L.ncu = s->ncu;
     L.stream = s->st;
     return L;
 }
@@ -1562,6 +1569,13 @@ static int bfail(pic_batch* b, int code, const char* msg)
     return code;
 }
 
+// the batch's particle-kernel unit queue: in the zeroed counter block after the idle entry's words
+static unsigned* batch_queue(const pic_batch* b)
+{
+    static_assert(64 + sizeof(unsigned) * kUnitQueueWords <= kIdleBytes, "queue in the counter block");
+    return reinterpret_cast<unsigned*>(static_cast<char*>(b->idle) + 64);
+}
+
 static SimDev idle_entry(const pic_batch* b)
 {
     SimDev e{};
@@ -1803,6 +1817,8 @@ static int batch_capture(pic_batch* b)
     L.ext = b->g_ext;
     for (int a = 0; a < 3; ++a) L.tile[a] = b->g_tile[a];
     L.permask = b->g_permask;
+    L.queue = batch_queue(b);
+    L.ncu = b->ncu;
     L.stream = b->st;
     const bool f32 = b->precision == PIC_FP32;
     if (hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal) != hipSuccess)

@@ -51,6 +51,12 @@ struct FieldTile<2> { static constexpr int X = 61, Y = 5, Z = 1; };  // row-swee
 constexpr int kSweepRowsEps = 6;
 template <>
 struct FieldTile<3> { static constexpr int X = 61, Y = 3, Z = 10; };  // plane-march task: 61 columns, 3 rows, 10 planes
+// XCDs of the MI355X: workgroups are dispatched to them round-robin
+constexpr int kXcds = 8;
+// device words of a particle-kernel unit queue: a next-unit counter and a finished-block counter
+// per XCD (zero between launches)
+constexpr int kUnitQueueWords = 2 * kXcds;
+
 // rows of a plane-march task in the FP64 form (its slabs of doubles take twice the registers: with
 // three rows it held one wavefront per SIMD)
 constexpr int kPlaneRowsFp64 = 2;
@@ -254,6 +260,8 @@ struct Launch {
     long long tensor_lvol; // field nodes of a simulation with a full tensor (0: none; a batch launches
                            // each tensor member's passes itself, through Launchers::tensor)
     int tile[3];           // the particle tile shape shared by every member (0 if they differ)
+    unsigned* queue;       // the particle kernel's unit queue (kUnitQueueWords, zero between launches)
+    int ncu;               // compute units of the device (the particle grid is fitted to them; 0: L.pgrid)
     int permask;           // the members' periodic active axes, a bit per axis (-1 if they differ)
     hipStream_t stream;
 };
