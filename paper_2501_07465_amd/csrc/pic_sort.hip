@@ -67,6 +67,7 @@ __global__ void __launch_bounds__(kSortBlock) k_radix_hist(SimDev* __restrict__ 
 // Exclusive scan of hist[0 .. kRadix * nb) (digit-major), one block per digit: each row scanned with
 // its offset, the sum of the totals of the lower digits (the totals come from the histogram pass).
 constexpr int kScanThreads = 1024;
+constexpr int kUnitBlock = 4;  // tiles per active axis of a block of the unit list
 
 // inclusive scan of v over the block (kScanThreads threads): DPP wavefront scans, then the wave
 // totals in order; *total receives the block total
@@ -273,10 +274,44 @@ constexpr int kCompactK = 4;
 __global__ void __launch_bounds__(kScanThreads) k_compact(SimDev* __restrict__ S)
 {
     __shared__ int wsum[kScanThreads / 64];
-    const int nt = S->ntiles;
     const int U = S->unit_cap;
     const int tid = threadIdx.x;
     constexpr int R = kCompactK * kScanThreads;
+    // Tiles are listed in blocks of kUnitBlock tiles along each active axis (x fastest inside a
+    // block, blocks in x-fastest order), so that tiles near each other along every axis are near
+    // each other in the list, and the particle kernel, which takes units in list order on each XCD,
+    // processes them close together in time (their shared window halos meet in L2).  Ranks run over
+    // the grid of tiles padded to whole blocks; a rank whose tile lies beyond the grid is skipped.
+    // A thread's kCompactK consecutive ranks lie in one block (a block holds a multiple of
+    // kCompactK ranks), so the block's position is divided out once per thread and round and the
+    // tiles inside it follow by shifts.
+    static_assert((kUnitBlock & (kUnitBlock - 1)) == 0 && kUnitBlock % kCompactK == 0, "blocks of whole thread runs");
+    constexpr int kBS = kUnitBlock == 4 ? 2 : (kUnitBlock == 8 ? 3 : 1);  // log2 of kUnitBlock
+    int sh[3], nb[3];
+    for (int a = 0; a < 3; ++a) {
+        sh[a] = a < S->dims ? kBS : 0;
+        nb[a] = (S->ntile[a] + (1 << sh[a]) - 1) >> sh[a];
+    }
+    const int vsh = sh[0] + sh[1] + sh[2];           // log2 of the ranks per block
+    const int nt = (nb[0] * nb[1] * nb[2]) << vsh;   // padded ranks
+    // the tiles of ranks r .. r + kCompactK - 1 (-1 beyond the grid)
+    auto tiles_of = [&](int r, int (&t)[kCompactK]) {
+        const int blk = r >> vsh;
+        const int b1 = blk / nb[0];
+        const int o0 = (blk - b1 * nb[0]) << sh[0];
+        const int b2 = b1 / nb[1];
+        const int o1 = (b1 - b2 * nb[1]) << sh[1], o2 = b2 << sh[2];
+#pragma unroll
+        for (int j = 0; j < kCompactK; ++j) {
+            const int w = (r + j) & ((1 << vsh) - 1);
+            const int c0 = o0 + (w & ((1 << sh[0]) - 1));
+            const int c1 = o1 + ((w >> sh[0]) & ((1 << sh[1]) - 1));
+            const int c2 = o2 + (w >> (sh[0] + sh[1]));
+            t[j] = r + j < nt && c0 < S->ntile[0] && c1 < S->ntile[1] && c2 < S->ntile[2]
+                       ? (c2 * S->ntile[1] + c1) * S->ntile[0] + c0
+                       : -1;
+        }
+    };
     auto count = [&](int t) {
         int c = 0;
         for (int s = 0; s < S->nspecies; ++s) c += S->sp[s].tile_start[t + 1] - S->sp[s].tile_start[t];
@@ -285,12 +320,13 @@ __global__ void __launch_bounds__(kScanThreads) k_compact(SimDev* __restrict__ S
     auto nunits = [&](int c) { return c == 0 ? 0 : (U > 0 ? (c + U - 1) / U : 1); };
     // totals
     int ca = 0, cu = 0;
-    for (int base = 0; base < nt; base += R) {
+    for (int base = 0; base < S->ntiles; base += R) {
+        // the totals do not depend on the order: tiles in index order here (coalesced reads)
         int c[kCompactK];
 #pragma unroll
         for (int j = 0; j < kCompactK; ++j) {
             const int t = base + tid * kCompactK + j;
-            c[j] = t < nt ? count(t) : 0;
+            c[j] = t < S->ntiles ? count(t) : 0;
         }
 #pragma unroll
         for (int j = 0; j < kCompactK; ++j) {
@@ -306,12 +342,12 @@ __global__ void __launch_bounds__(kScanThreads) k_compact(SimDev* __restrict__ S
     const bool fits = ta <= S->max_slots && tu <= S->max_units;
     int oa = 0, ou = 0;  // active tiles and units of the rounds before
     for (int base = 0; base < nt; base += R) {
-        int c[kCompactK];
+        int c[kCompactK], tt[kCompactK];
         int ra = 0, ru = 0;
+        tiles_of(base + tid * kCompactK, tt);
 #pragma unroll
         for (int j = 0; j < kCompactK; ++j) {
-            const int t = base + tid * kCompactK + j;
-            c[j] = t < nt ? count(t) : 0;
+            c[j] = tt[j] >= 0 ? count(tt[j]) : 0;
             ra += c[j] > 0 ? 1 : 0;
             ru += nunits(c[j]);
         }
@@ -320,8 +356,8 @@ __global__ void __launch_bounds__(kScanThreads) k_compact(SimDev* __restrict__ S
         int pu = block_scan(ru, wsum, &su) - ru + ou;
 #pragma unroll
         for (int j = 0; j < kCompactK; ++j) {
-            const int t = base + tid * kCompactK + j;
-            if (t >= nt) continue;
+            const int t = tt[j];
+            if (t < 0) continue;
             if (c[j] > 0 && fits) {
                 const int k = nunits(c[j]);
                 S->active[pa] = t;
