@@ -34,11 +34,13 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 CALIB_KERNEL = "MulFunctor"  # torch's vectorized elementwise kernel of the calibration multiply
 SOA_KERNEL = "k_measure_soa_copy"  # the library's structure-of-arrays calibration copy
-KERNEL_SOURCES = ("csrc/pic_kernels.inc", "csrc/pic_internal.h", "csrc/pic_k32.hip", "csrc/pic_k64.hip")
+# the kernels, and the host code and sort that decide their launches and the order of their work
+KERNEL_SOURCES = ("csrc/pic_kernels.inc", "csrc/pic_internal.h", "csrc/pic_k32.hip", "csrc/pic_k64.hip",
+                  "csrc/pic_dpp.h", "csrc/pic_sort.hip", "csrc/pic_sort.h", "csrc/pic_host.hip")
 
 
 def source_digest() -> str:
-    """SHA-256 over the sources of the particle and field kernels (counters go stale when it changes)."""
+    """SHA-256 over the sources that decide what the profiled kernels do (counters go stale when it changes)."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
         with open(os.path.join(HERE, rel), "rb") as f:
