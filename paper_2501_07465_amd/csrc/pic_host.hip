@@ -1020,7 +1020,7 @@ static int enqueue_sort_all(pic_sim* s, std::vector<int>* sorted)
         x.sorted_once = true;
         if (sorted) sorted->push_back((int)i);
     }
-    HIPCHK(s, enqueue_compact(s->d, s->st));
+    HIPCHK(s, enqueue_compact(s->d, s->h, s->st));
     s->need_sort = false;
     return PIC_OK;
 }

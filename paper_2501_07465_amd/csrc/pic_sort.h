@@ -24,6 +24,6 @@ hipError_t enqueue_ranges(SimDev* dS, int s, int ntiles, int passes, bool swap, 
 // Keys of species s into its key buffer (diagnostics).
 hipError_t enqueue_keys_only(SimDev* dS, int s, int n, hipStream_t st);
 // Active tile list and slots.
-hipError_t enqueue_compact(SimDev* dS, hipStream_t st);
+hipError_t enqueue_compact(SimDev* dS, const SimDev& h, hipStream_t st);
 
 }  // namespace pic

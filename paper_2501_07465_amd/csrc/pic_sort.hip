@@ -263,39 +263,45 @@ __global__ void k_tile_ranges(SimDev* __restrict__ S, int s, int passes, int swa
     }
 }
 
-// Active tiles (any species has particles) in tile order, and their work units: a tile holding
-// c particles (all species) gets ceil(c / U) units of at most U particles, in its species-
-// concatenated order (one unit when U is 0); the units of a tile take consecutive slots.
-// One block, rounds of kCompactK * 1024 tiles (each thread kCompactK consecutive tiles): a first
-// sweep forms the totals (whether the lists fit), a second places the tiles and units of each
-// round with block scans.
+// Active tiles (any species has particles) and their work units: a tile holding c particles (all
+// species) gets ceil(c / U) units of at most U particles, in its species-concatenated order (one
+// unit when U is 0); the units of a tile take consecutive slots.
+//
+// Tiles are listed in blocks of kUnitBlock tiles along each active axis (x fastest inside a block,
+// blocks in x-fastest order), so that tiles near each other along every axis are near each other
+// in the list, and the particle kernel, which takes units in list order on each XCD, processes them
+// close together in time (their shared window halos meet in L2).  Ranks run over the grid of tiles
+// padded to whole blocks; a rank whose tile lies beyond the grid is skipped.
+//
+// A list of one round is built by one block in one launch (k_compact_one).  Longer lists take
+// three launches over rounds of kCompactK * 1024 ranks (each thread kCompactK consecutive ranks),
+// each block of the first and last taking a contiguous run of rounds: k_compact_count forms each
+// block's totals of active tiles and units, k_compact_scan their exclusive prefix in block order
+// (and whether the lists fit), k_compact_place places the tiles and units of each round with a
+// block scan from its block's prefix.  The block totals and prefixes live in sort_part, which every
+// sort clears at its start.
 constexpr int kCompactK = 4;
+constexpr int kCompactBlocks = kPartCopies * kRadix / 2 - 1;  // block totals in sort_part (its last word: the fit flag)
 
-__global__ void __launch_bounds__(kScanThreads) k_compact(SimDev* __restrict__ S)
-{
-    __shared__ int wsum[kScanThreads / 64];
-    const int U = S->unit_cap;
-    const int tid = threadIdx.x;
-    constexpr int R = kCompactK * kScanThreads;
-    // Tiles are listed in blocks of kUnitBlock tiles along each active axis (x fastest inside a
-    // block, blocks in x-fastest order), so that tiles near each other along every axis are near
-    // each other in the list, and the particle kernel, which takes units in list order on each XCD,
-    // processes them close together in time (their shared window halos meet in L2).  Ranks run over
-    // the grid of tiles padded to whole blocks; a rank whose tile lies beyond the grid is skipped.
-    // A thread's kCompactK consecutive ranks lie in one block (a block holds a multiple of
-    // kCompactK ranks), so the block's position is divided out once per thread and round and the
-    // tiles inside it follow by shifts.
-    static_assert((kUnitBlock & (kUnitBlock - 1)) == 0 && kUnitBlock % kCompactK == 0, "blocks of whole thread runs");
-    constexpr int kBS = kUnitBlock == 4 ? 2 : (kUnitBlock == 8 ? 3 : 1);  // log2 of kUnitBlock
-    int sh[3], nb[3];
-    for (int a = 0; a < 3; ++a) {
-        sh[a] = a < S->dims ? kBS : 0;
-        nb[a] = (S->ntile[a] + (1 << sh[a]) - 1) >> sh[a];
+struct CompactGeom {
+    int sh[3], nb[3], vsh, nt, rounds, rpb;
+    __device__ __forceinline__ explicit CompactGeom(const SimDev* S)
+    {
+        static_assert((kUnitBlock & (kUnitBlock - 1)) == 0 && kUnitBlock % kCompactK == 0, "blocks of whole thread runs");
+        constexpr int kBS = kUnitBlock == 4 ? 2 : (kUnitBlock == 8 ? 3 : 1);  // log2 of kUnitBlock
+        for (int a = 0; a < 3; ++a) {
+            sh[a] = a < S->dims ? kBS : 0;
+            nb[a] = (S->ntile[a] + (1 << sh[a]) - 1) >> sh[a];
+        }
+        vsh = sh[0] + sh[1] + sh[2];                 // log2 of the ranks per block
+        nt = (nb[0] * nb[1] * nb[2]) << vsh;         // padded ranks
+        rounds = (nt + kCompactK * kScanThreads - 1) / (kCompactK * kScanThreads);
+        rpb = (rounds + gridDim.x - 1) / gridDim.x;  // rounds per block
     }
-    const int vsh = sh[0] + sh[1] + sh[2];           // log2 of the ranks per block
-    const int nt = (nb[0] * nb[1] * nb[2]) << vsh;   // padded ranks
-    // the tiles of ranks r .. r + kCompactK - 1 (-1 beyond the grid)
-    auto tiles_of = [&](int r, int (&t)[kCompactK]) {
+    // the tiles of ranks r .. r + kCompactK - 1 (-1 beyond the grid); they lie in one block of the
+    // list (a block holds a multiple of kCompactK ranks), so its position is divided out once
+    __device__ __forceinline__ void tiles_of(const SimDev* S, int r, int (&t)[kCompactK]) const
+    {
         const int blk = r >> vsh;
         const int b1 = blk / nb[0];
         const int o0 = (blk - b1 * nb[0]) << sh[0];
@@ -311,45 +317,146 @@ __global__ void __launch_bounds__(kScanThreads) k_compact(SimDev* __restrict__ S
                        ? (c2 * S->ntile[1] + c1) * S->ntile[0] + c0
                        : -1;
         }
-    };
-    auto count = [&](int t) {
-        int c = 0;
-        for (int s = 0; s < S->nspecies; ++s) c += S->sp[s].tile_start[t + 1] - S->sp[s].tile_start[t];
-        return c;
-    };
-    auto nunits = [&](int c) { return c == 0 ? 0 : (U > 0 ? (c + U - 1) / U : 1); };
-    // totals
+    }
+};
+
+__device__ __forceinline__ int compact_count(const SimDev* S, int t)
+{
+    int c = 0;
+    for (int s = 0; s < S->nspecies; ++s) c += S->sp[s].tile_start[t + 1] - S->sp[s].tile_start[t];
+    return c;
+}
+__device__ __forceinline__ int compact_units(const SimDev* S, int c)
+{
+    return c == 0 ? 0 : (S->unit_cap > 0 ? (c + S->unit_cap - 1) / S->unit_cap : 1);
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_compact_count(SimDev* __restrict__ S)
+{
+    __shared__ int wsum[kScanThreads / 64];
+    const CompactGeom G(S);
     int ca = 0, cu = 0;
-    for (int base = 0; base < S->ntiles; base += R) {
-        // the totals do not depend on the order: tiles in index order here (coalesced reads)
-        int c[kCompactK];
+    const int r0 = blockIdx.x * G.rpb, r1 = min(G.rounds, r0 + G.rpb);
+    for (int round = r0; round < r1; ++round) {
+        int t[kCompactK];
+        G.tiles_of(S, round * kCompactK * kScanThreads + threadIdx.x * kCompactK, t);
 #pragma unroll
         for (int j = 0; j < kCompactK; ++j) {
-            const int t = base + tid * kCompactK + j;
-            c[j] = t < S->ntiles ? count(t) : 0;
-        }
-#pragma unroll
-        for (int j = 0; j < kCompactK; ++j) {
-            ca += c[j] > 0 ? 1 : 0;
-            cu += nunits(c[j]);
+            const int c = t[j] >= 0 ? compact_count(S, t[j]) : 0;
+            ca += c > 0 ? 1 : 0;
+            cu += compact_units(S, c);
         }
     }
     int ta, tu;
     block_scan(ca, wsum, &ta);
     block_scan(cu, wsum, &tu);
-    // a list that does not fit (particles in tiles the capacity did not count) is dropped whole
-    // and flagged: no particle moves this period
+    if (threadIdx.x == 0) {
+        S->sort_part[2 * blockIdx.x] = ta;
+        S->sort_part[2 * blockIdx.x + 1] = tu;
+    }
+}
+
+// one block: the blocks' exclusive prefixes in place of their totals, the list lengths, and whether
+// the lists fit (a list that does not fit, with particles in tiles the capacity did not count, is
+// dropped whole and flagged: no particle moves this period)
+__global__ void __launch_bounds__(kScanThreads) k_compact_scan(SimDev* __restrict__ S, int nblocks)
+{
+    __shared__ int wsum[kScanThreads / 64];
+    __shared__ int carry[2];
+    if (threadIdx.x < 2) carry[threadIdx.x] = 0;
+    __syncthreads();
+    for (int base = 0; base < nblocks; base += kScanThreads) {
+        const int b = base + threadIdx.x;
+        const int a = b < nblocks ? S->sort_part[2 * b] : 0, u = b < nblocks ? S->sort_part[2 * b + 1] : 0;
+        int sa, su;
+        const int pa = block_scan(a, wsum, &sa) - a + carry[0];
+        const int pu = block_scan(u, wsum, &su) - u + carry[1];
+        if (b < nblocks) {
+            S->sort_part[2 * b] = pa;
+            S->sort_part[2 * b + 1] = pu;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            carry[0] += sa;
+            carry[1] += su;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int ta = carry[0], tu = carry[1];
+        const bool fits = ta <= S->max_slots && tu <= S->max_units;
+        S->sort_part[kPartCopies * kRadix - 1] = fits ? 1 : 0;
+        *S->n_active = fits ? ta : 0;
+        *S->n_units = fits ? tu : 0;
+        if (!fits) atomicAdd(S->over_count, 1ull << 40);
+    }
+}
+
+// A list of one round (small grids): the three steps in one block and one launch.
+__global__ void __launch_bounds__(kScanThreads) k_compact_one(SimDev* __restrict__ S)
+{
+    __shared__ int wsum[kScanThreads / 64];
+    const CompactGeom G(S);
+    const int U = S->unit_cap;
+    int c[kCompactK], tt[kCompactK];
+    int ra = 0, ru = 0;
+    G.tiles_of(S, threadIdx.x * kCompactK, tt);
+#pragma unroll
+    for (int j = 0; j < kCompactK; ++j) {
+        c[j] = tt[j] >= 0 ? compact_count(S, tt[j]) : 0;
+        ra += c[j] > 0 ? 1 : 0;
+        ru += compact_units(S, c[j]);
+    }
+    int ta, tu;
+    int pa = block_scan(ra, wsum, &ta) - ra;
+    int pu = block_scan(ru, wsum, &tu) - ru;
     const bool fits = ta <= S->max_slots && tu <= S->max_units;
-    int oa = 0, ou = 0;  // active tiles and units of the rounds before
-    for (int base = 0; base < nt; base += R) {
+#pragma unroll
+    for (int j = 0; j < kCompactK; ++j) {
+        const int t = tt[j];
+        if (t < 0) continue;
+        if (c[j] > 0 && fits) {
+            const int k = compact_units(S, c[j]);
+            S->active[pa] = t;
+            S->tile_slot[t] = pu;
+            S->tile_nslot[t] = k;
+            for (int q = 0; q < k; ++q) {
+                int* u = S->units + 3 * (pu + q);
+                u[0] = t;
+                u[1] = U > 0 ? q * U : 0;
+                u[2] = U > 0 ? min(c[j], (q + 1) * U) : c[j];
+            }
+            ++pa;
+            pu += k;
+        } else {
+            S->tile_slot[t] = -1;
+            S->tile_nslot[t] = 0;
+        }
+    }
+    if (threadIdx.x == 0) {
+        *S->n_active = fits ? ta : 0;
+        *S->n_units = fits ? tu : 0;
+        if (!fits) atomicAdd(S->over_count, 1ull << 40);
+    }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_compact_place(SimDev* __restrict__ S)
+{
+    __shared__ int wsum[kScanThreads / 64];
+    const CompactGeom G(S);
+    const int U = S->unit_cap;
+    const bool fits = S->sort_part[kPartCopies * kRadix - 1] != 0;
+    int oa = S->sort_part[2 * blockIdx.x], ou = S->sort_part[2 * blockIdx.x + 1];  // the blocks before
+    const int r0 = blockIdx.x * G.rpb, r1 = min(G.rounds, r0 + G.rpb);
+    for (int round = r0; round < r1; ++round) {
         int c[kCompactK], tt[kCompactK];
         int ra = 0, ru = 0;
-        tiles_of(base + tid * kCompactK, tt);
+        G.tiles_of(S, round * kCompactK * kScanThreads + threadIdx.x * kCompactK, tt);
 #pragma unroll
         for (int j = 0; j < kCompactK; ++j) {
-            c[j] = tt[j] >= 0 ? count(tt[j]) : 0;
+            c[j] = tt[j] >= 0 ? compact_count(S, tt[j]) : 0;
             ra += c[j] > 0 ? 1 : 0;
-            ru += nunits(c[j]);
+            ru += compact_units(S, c[j]);
         }
         int sa, su;
         int pa = block_scan(ra, wsum, &sa) - ra + oa;
@@ -359,7 +466,7 @@ __global__ void __launch_bounds__(kScanThreads) k_compact(SimDev* __restrict__ S
             const int t = tt[j];
             if (t < 0) continue;
             if (c[j] > 0 && fits) {
-                const int k = nunits(c[j]);
+                const int k = compact_units(S, c[j]);
                 S->active[pa] = t;
                 S->tile_slot[t] = pu;
                 S->tile_nslot[t] = k;
@@ -378,11 +485,6 @@ __global__ void __launch_bounds__(kScanThreads) k_compact(SimDev* __restrict__ S
         }
         oa += sa;
         ou += su;
-    }
-    if (tid == 0) {
-        *S->n_active = fits ? ta : 0;
-        *S->n_units = fits ? tu : 0;
-        if (!fits) atomicAdd(S->over_count, 1ull << 40);
     }
 }
 
@@ -420,9 +522,24 @@ hipError_t enqueue_ranges(SimDev* dS, int s, int ntiles, int passes, bool swap, 
     return hipGetLastError();
 }
 
-hipError_t enqueue_compact(SimDev* dS, hipStream_t st)
+hipError_t enqueue_compact(SimDev* dS, const SimDev& h, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, st, dS);
+    // the padded ranks of the list (as CompactGeom counts them) and its rounds, over at most
+    // kCompactBlocks blocks
+    long long nt = 1;
+    for (int a = 0; a < 3; ++a) {
+        const int b = a < h.dims ? kUnitBlock : 1;
+        nt *= (long long)((h.ntile[a] + b - 1) / b) * b;
+    }
+    const long long rounds = (nt + kCompactK * kScanThreads - 1) / (kCompactK * kScanThreads);
+    if (rounds <= 1) {
+        hipLaunchKernelGGL(k_compact_one, dim3(1), dim3(kScanThreads), 0, st, dS);
+        return hipGetLastError();
+    }
+    const int nb = (int)(rounds < kCompactBlocks ? rounds : kCompactBlocks);
+    hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(kScanThreads), 0, st, dS);
+    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(kScanThreads), 0, st, dS, nb);
+    hipLaunchKernelGGL(k_compact_place, dim3(nb), dim3(kScanThreads), 0, st, dS);
     return hipGetLastError();
 }
 
