@@ -4,13 +4,13 @@
 
 namespace pic {
 
-// Keys per radix-sort block: 4096, doubled until at most 4096 blocks cover n keys (the digit
+// Keys per radix-sort block: 4096, doubled until at most 2048 blocks cover n keys (the digit
 // histogram holds 256 counts per block), and for small sorts halved down to 1024 (one key per
 // thread) while fewer than 512 blocks would cover them, so that the blocks fill the 256 CUs.
 inline int sort_ipb(long long n)
 {
     long long ipb = 4096;
-    while ((n + ipb - 1) / ipb > 4096) ipb *= 2;
+    while ((n + ipb - 1) / ipb > 2048) ipb *= 2;
     while (ipb > 1024 && (n + ipb - 1) / ipb < 512) ipb /= 2;
     return (int)ipb;
 }

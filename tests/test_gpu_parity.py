@@ -154,6 +154,37 @@ def test_sort_order_bit_exact(oracle):
         assert float(np.max(np.abs(xg - xr) / np.array(w["dx"]))) < 1e-12
 
 
+def test_sort_of_many_keys_is_stable():
+    """A sort over many blocks with several rounds of keys each (9M particles in random order on a
+    periodic 64^3 grid: 18-bit keys, three 8-bit passes) leaves the particles in the order of a
+    stable argsort of their cell keys, bit for bit.  Velocities and fields are zero, so the step
+    that follows the sort moves nothing."""
+    from paper_2501_07465_amd import pic
+    from paper_2501_07465_amd import workloads as W
+    w = W.sphere3d(n=64, steps=1)
+    w["periodic"] = [1, 1, 1]
+    w.pop("source")
+    w["species"] = [W.free_electrons(1, 5.5, 300.0, reflect=False)]
+    w["sort_every"] = 1
+    w["ion"] = "uniform"
+    n = 9_000_000
+    rng = np.random.default_rng(11)
+    x = rng.random((n, 3)) * (np.array(w["n"]) * np.array(w["dx"]))
+    zero = np.zeros((3, 64, 64, 64))
+    print("case sort of 9M keys", flush=True)
+    sim = pic.Simulation(w, states=[(x, np.zeros((n, 3)), None, 1.0)], fields=(zero, zero), graphs=False)
+    assert sim.shape() == (64, 64, 64)
+    x0, _, _ = sim.particles(0)
+    k0 = sim.keys(0)
+    assert k0.max() >= 2 ** 16  # the third pass has digits to sort
+    order = np.argsort(k0, kind="stable")
+    sim.step(1)
+    x1, v1, _ = sim.particles(0)
+    assert not np.any(v1)
+    assert np.array_equal(sim.keys(0), k0[order])
+    assert np.array_equal(x1, x0[order])
+
+
 @pytest.mark.parametrize("name,tile", [("disk2d", None), ("sheet2d", None), ("sphere3d", None), ("slab1d", None),
                                        # the tile shapes compiled with constant window geometry
                                        ("disk2d", [32, 32, 1]), ("sphere3d", [4, 4, 4])])
