@@ -20,7 +20,8 @@ constexpr int kSortBlock = 1024;
 // that fewer blocks queue on each address; the row scan sums the copies
 constexpr int kPartCopies = 8;
 
-// keys[i] = tile-major key of particle i's cell (anchor cell for bound particles); vals[i] = i.
+// keys[i] = tile-major key of particle i's cell (anchor cell for bound particles).  The values the
+// passes carry start as the identity, which the first scatter pass forms from the index (not stored).
 // Block 0 also clears the digit totals the first histogram pass adds into.
 __global__ void k_keys(SimDev* __restrict__ S, int s)
 {
@@ -32,7 +33,6 @@ __global__ void k_keys(SimDev* __restrict__ S, int s)
         int c[3];
         unpack_cell(*S, sp.cell[i], c);
         sp.keys[i] = cell_key(*S, c);
-        sp.vals[i] = i;
     }
 }
 
@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(kSortBlock) k_radix_scatter(SimDev* __restrict
         int key = 0, val = 0, d = 0;
         if (act) {
             key = kin[i];
-            val = vin[i];
+            val = pass == 0 ? i : vin[i];  // the first pass carries each key's own index
             d = (key >> shift) & (kRadix - 1);
         }
         // lanes of this wave holding the same digit
