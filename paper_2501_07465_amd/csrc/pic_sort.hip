@@ -133,11 +133,18 @@ __global__ void __launch_bounds__(kScanThreads) k_radix_rowscan(SimDev* __restri
     }
 }
 
-// stable scatter of one pass
+// Stable scatter of one pass, in rounds of K keys per thread (key j of thread t in a round is the
+// round's key j * kSortBlock + t, so the keys of a round are taken in input order item by item).
+// Each wavefront ranks its lanes' equal digits with ballots and its first lane of each digit
+// stores the count; one thread per digit then turns the (item, wave) counts of its digit, in
+// input order, into the slot of each group's first key, and every key goes to that slot plus its
+// rank.  Four barriers per round: K = 4 for blocks of at least 4096 keys, 1 for smaller ones.
+template <int K>
 __global__ void __launch_bounds__(kSortBlock) k_radix_scatter(SimDev* __restrict__ S, int s, int pass, int ipb)
 {
+    constexpr int NW = kSortBlock / 64;
     __shared__ int running[kRadix];
-    __shared__ int wcnt[kSortBlock / 64][kRadix];
+    __shared__ int wcnt[K][NW][kRadix];
     const SpeciesDev& sp = S->sp[s];
     const int* kin = (pass & 1) ? sp.keys_alt : sp.keys;
     const int* vin = (pass & 1) ? sp.vals_alt : sp.vals;
@@ -152,47 +159,53 @@ __global__ void __launch_bounds__(kSortBlock) k_radix_scatter(SimDev* __restrict
         for (int d = threadIdx.x; d < kPartCopies * kRadix; d += blockDim.x) S->sort_part[d] = 0;
     const int shift = pass * kRadixBits;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nw = blockDim.x / 64;
     for (int d = threadIdx.x; d < kRadix; d += blockDim.x) running[d] = S->sort_hist[d * nb + b];
-    for (int i = threadIdx.x; i < nw * kRadix; i += blockDim.x) wcnt[i / kRadix][i % kRadix] = 0;
-    __syncthreads();
     const int lo = b * ipb, hi = min(n, lo + ipb);
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int base = lo; base < hi; base += blockDim.x) {
-        const int i = base + threadIdx.x;
-        const bool act = i < hi;
-        int key = 0, val = 0, d = 0;
-        if (act) {
-            key = kin[i];
-            val = pass == 0 ? i : vin[i];  // the first pass carries each key's own index
-            d = (key >> shift) & (kRadix - 1);
-        }
-        // lanes of this wave holding the same digit
-        unsigned long long peers = __ballot(act);
+    for (int base = lo; base < hi; base += K * kSortBlock) {
+        for (int i = threadIdx.x; i < K * NW * kRadix; i += blockDim.x) (&wcnt[0][0][0])[i] = 0;
+        int key[K], val[K], d[K], rank[K];
+        bool act[K];
 #pragma unroll
-        for (int bit = 0; bit < kRadixBits; ++bit) {
-            const unsigned long long m = __ballot(act && ((d >> bit) & 1));
-            peers &= ((d >> bit) & 1) ? m : ~m;
+        for (int j = 0; j < K; ++j) {
+            const int i = base + j * kSortBlock + (int)threadIdx.x;
+            act[j] = i < hi;
+            key[j] = act[j] ? kin[i] : 0;
+            val[j] = act[j] ? (pass == 0 ? i : vin[i]) : 0;  // the first pass carries each key's own index
+            d[j] = (key[j] >> shift) & (kRadix - 1);
         }
-        const int rank = __popcll(peers & lt);
-        const int cnt = __popcll(peers);
-        if (act && rank == 0) wcnt[wave][d] = cnt;
         __syncthreads();
-        if (act) {
-            int off = running[d] + rank;
-            for (int w = 0; w < wave; ++w) off += wcnt[w][d];
-            kout[off] = key;
-            vout[off] = val;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            // lanes of this wave holding the same digit
+            unsigned long long peers = __ballot(act[j]);
+#pragma unroll
+            for (int bit = 0; bit < kRadixBits; ++bit) {
+                const unsigned long long m = __ballot(act[j] && ((d[j] >> bit) & 1));
+                peers &= ((d[j] >> bit) & 1) ? m : ~m;
+            }
+            rank[j] = __popcll(peers & lt);
+            if (act[j] && rank[j] == 0) wcnt[j][wave][d[j]] = __popcll(peers);
         }
         __syncthreads();
         for (int dd = threadIdx.x; dd < kRadix; dd += blockDim.x) {
-            int t = 0;
-            for (int w = 0; w < nw; ++w) {
-                t += wcnt[w][dd];
-                wcnt[w][dd] = 0;
-            }
-            running[dd] += t;
+            int acc = running[dd];
+            for (int j = 0; j < K; ++j)
+                for (int w = 0; w < NW; ++w) {
+                    const int c = wcnt[j][w][dd];
+                    wcnt[j][w][dd] = acc;
+                    acc += c;
+                }
+            running[dd] = acc;
         }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (act[j]) {
+                const int off = wcnt[j][wave][d[j]] + rank[j];
+                kout[off] = key[j];
+                vout[off] = val[j];
+            }
         __syncthreads();
     }
 }
@@ -501,7 +514,10 @@ hipError_t enqueue_sort(SimDev* dS, int s, int n, int passes, int elem, hipStrea
             hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortBlock), 0, st, dS, s, p, ipb, fuse);
             if (!fuse) hipLaunchKernelGGL(k_radix_rowsum, dim3(kRadix), dim3(kScanThreads), 0, st, dS, s, ipb);
             hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(kScanThreads), 0, st, dS, s, ipb);
-            hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortBlock), 0, st, dS, s, p, ipb);
+            if (ipb >= 4 * kSortBlock)
+                hipLaunchKernelGGL(k_radix_scatter<4>, dim3(nb), dim3(kSortBlock), 0, st, dS, s, p, ipb);
+            else
+                hipLaunchKernelGGL(k_radix_scatter<1>, dim3(nb), dim3(kSortBlock), 0, st, dS, s, p, ipb);
         }
         hipLaunchKernelGGL(k_permute, dim3(g > 0 ? g : 1), dim3(256), 0, st, dS, s, passes, elem);
     }
